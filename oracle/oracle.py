@@ -1,0 +1,360 @@
+"""FP64 oracle of the RenderMap pose-scoring path (arXiv 1702.06813).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``.  The product library never
+imports, links or calls anything here, and this module shares no code with it.
+
+Pieces, each following the paper:
+  * scan image and meshification (Sec. IV-A) and the brute-force z-buffer
+    R(T(X)) of Eq. (1): the C file ``rm_oracle.c`` next to this module;
+  * the per-pixel comparison C of Table I (Sec. IV-B) with epsilon = 0.1 m,
+    and the total error E(X) = sum over pixels (Sec. IV-B);
+  * E_soft, a continuous surrogate of E(X) (the paper invites reshaping the
+    per-pixel cost, Sec. IV-C) with its se(3) gradient and the Gauss-Newton
+    blocks J^T J / J^T r; and SE(3) exp for pose increments.
+
+E_soft (a project definition; the paper optimizes E derivative-free):
+    rho_p = 2 * min(r_p^2 / eps^2, 1) - 1   on the three scored cells,
+    rho_p = 0                              on ignored cells, with
+    r_p = dz          (map FO, scan FO)
+    r_p = min(dz, 0)  (map FO, scan FU: penalty side is dz <= 0)
+    r_p = max(dz, 0)  (map FU, scan FO: penalty side is dz > 0)
+    dz  = d(p_r) - d(p_s)  (Table I).
+rho equals Table I's +1 once |r| >= eps and -1 where the Table I cell is a
+reward with r = 0.  A pixel is *active* when its residual moves with the pose:
+scored, r^2 < eps^2, and (FO/FO, or FO/FU with dz < 0, or FU/FO with dz > 0).
+    grad E_soft = (4 / eps^2) * sum_active r_p J_p
+    H = sum_active J_p^T J_p ,  b = sum_active r_p J_p
+J_p is the derivative of the rendered depth at pixel p with respect to a
+right perturbation T_wc * exp(delta), delta = (upsilon, omega):
+    J_p = [ -n ; n x P ] / (n . r),   P = z r,  r = ((u-cx)/fx, (v-cy)/fy, 1)
+with n the winning triangle's camera-frame plane normal.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+HERE = Path(__file__).resolve().parent
+SRC = HERE / "rm_oracle.c"
+LIB = HERE / "liboracle.so"
+
+FO, FU, UO, NONE = 0, 1, 2, 3
+
+# Table I cell indices of the per-pose counts
+CELL_NAMES = ["FO/FO reward", "FO/FO penalty", "FO/FU reward", "FO/FU penalty",
+              "FU/FO reward", "FU/FO penalty", "ignore: scan NaN", "ignore: map NaN or UO",
+              "ignore: FU/FU"]
+
+# tolerances that define the flagged pixels (see the tests that use them)
+NEAR_TIE_REL = 1e-6       # depth near-tie between the two nearest surfaces
+DEPTH_REL = 1e-5          # depth agreement; also the width of a threshold tie
+GRAZING_COS = 1e-2        # |n^ . r^| below this: grazing view of the winner
+
+
+def build(force: bool = False) -> Path:
+    """Compile the C part of the oracle with gcc (OpenMP, no FP contraction)."""
+    if force or not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+               "-shared", "-fPIC", "-o", str(LIB), str(SRC), "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("z_near", ctypes.c_float), ("z_far", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not LIB.exists():
+            build()
+        L = ctypes.CDLL(str(LIB))
+        P = ctypes.c_void_p
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_scan_image.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, P, P]
+        L.or_meshify.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_Cam), P,
+                                 ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 P, P, P, ctypes.c_int64, P]
+        L.or_meshify.restype = ctypes.c_int64
+        L.or_render.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.POINTER(_Cam),
+                                ctypes.c_int32, P, ctypes.c_int64, P, P, P, P, P]
+        L.or_render.restype = ctypes.c_int64
+        L.or_contract_subs.argtypes = [P, P, ctypes.c_int64, P, ctypes.POINTER(_Cam), P, ctypes.c_int64]
+        L.or_contract_subs.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _cam(cam) -> _Cam:
+    fx, fy, cx, cy, W, H, zn, zf = cam.astuple() if hasattr(cam, "astuple") else cam
+    return _Cam(fx, fy, cx, cy, int(W), int(H), zn, zf)
+
+
+def _pose(T):
+    return np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(12))
+
+
+# --------------------------------------------------------------------------
+# Sec. IV-A: scan image and meshification
+# --------------------------------------------------------------------------
+
+def scan_image(depth, z_min=0.5, z_max=8.0):
+    """(d_s f32 [H,W], c_s u8 [H,W]) from a range image."""
+    depth = np.ascontiguousarray(depth, dtype=np.float32)
+    H, W = depth.shape
+    d = np.empty((H, W), np.float32)
+    c = np.empty((H, W), np.uint8)
+    lib().or_scan_image(_ptr(depth), H, W, z_min, z_max, _ptr(d), _ptr(c))
+    return d, c
+
+
+def meshify(depth, cam, T_wc, stride, z_min=0.5, z_max=8.0, max_edge=0.1):
+    """Interface mesh (xyz f32 [V,3], tri i32 [T,3], cls u8 [T]) of a range image."""
+    depth = np.ascontiguousarray(depth, dtype=np.float32)
+    H, W = depth.shape
+    gh, gw = -(-H // stride), -(-W // stride)
+    cap_t = 2 * max(gh - 1, 0) * max(gw - 1, 0)
+    xyz = np.empty((gh * gw, 3), np.float32)
+    tri = np.empty((max(cap_t, 1), 3), np.int32)
+    cls = np.empty(max(cap_t, 1), np.uint8)
+    nv = ctypes.c_int64(0)
+    c = _cam(cam)
+    nt = lib().or_meshify(_ptr(depth), H, W, ctypes.byref(c), _ptr(_pose(T_wc)), stride,
+                          z_min, z_max, max_edge, _ptr(xyz), _ptr(tri), _ptr(cls), cap_t,
+                          ctypes.byref(nv))
+    assert nt >= 0
+    return xyz, tri[:nt].copy(), cls[:nt].copy()
+
+
+# --------------------------------------------------------------------------
+# Eq. (1): brute-force z-buffer
+# --------------------------------------------------------------------------
+
+def render(mesh, cam, T_wc, pixels=None, mode="contract"):
+    """Z-buffer of ``mesh`` seen from ``T_wc`` at linear ``pixels`` (all if None).
+
+    Returns a dict of per-pixel arrays: z (NaN: no surface), id (-1), z2
+    (runner-up depth), ncov (covering triangles), nrm (winner camera-frame
+    normal) and the scalar ``dropped`` (sub-triangles beyond the snap range).
+    """
+    xyz, tri = (np.ascontiguousarray(mesh[0], np.float32), np.ascontiguousarray(mesh[1], np.int32))
+    W, H = cam.width, cam.height
+    if pixels is None:
+        n, pix = W * H, None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = pix.size
+    z = np.empty(n); z2 = np.empty(n); nrm = np.empty((n, 3))
+    ids = np.empty(n, np.int32); ncov = np.empty(n, np.int32)
+    c = _cam(cam)
+    dropped = lib().or_render(_ptr(xyz), xyz.shape[0], _ptr(tri), tri.shape[0], _ptr(_pose(T_wc)),
+                              ctypes.byref(c), 0 if mode == "contract" else 1, _ptr(pix), n,
+                              _ptr(z), _ptr(ids), _ptr(z2), _ptr(ncov), _ptr(nrm))
+    return dict(z=z, id=ids, z2=z2, ncov=ncov, nrm=nrm, dropped=int(dropped),
+                pixels=np.arange(W * H) if pixels is None else pix)
+
+
+def contract_subtriangles(mesh, cam, T_wc):
+    """The snapped sub-triangles of the rasterization contract for one pose:
+    int64 [N, 7] rows (parent id, X0, Y0, X1, Y1, X2, Y2) in 1/256 px."""
+    xyz, tri = np.ascontiguousarray(mesh[0], np.float32), np.ascontiguousarray(mesh[1], np.int32)
+    cap = 2 * tri.shape[0] + 1
+    out = np.empty((cap, 7), np.int64)
+    c = _cam(cam)
+    ns = lib().or_contract_subs(_ptr(xyz), _ptr(tri), tri.shape[0], _ptr(_pose(T_wc)),
+                                ctypes.byref(c), _ptr(out), cap)
+    return out[:ns].copy()
+
+
+def rays(cam, pixels):
+    """Camera-frame ray r = ((u-cx)/fx, (v-cy)/fy, 1) of each linear pixel, FP64."""
+    u = (pixels % cam.width).astype(np.float64)
+    v = (pixels // cam.width).astype(np.float64)
+    return np.stack([(u - np.float64(np.float32(cam.cx))) / np.float64(np.float32(cam.fx)),
+                     (v - np.float64(np.float32(cam.cy))) / np.float64(np.float32(cam.fy)),
+                     np.ones_like(u)], -1)
+
+
+def flags(rend, cam):
+    """Per-pixel flags of a render: near_tie, far_tie, grazing."""
+    z, z2 = rend["z"], rend["z2"]
+    hit = rend["id"] >= 0
+    zf = float(np.float32(cam.z_far))
+    with np.errstate(invalid="ignore"):
+        near = hit & (z2 - z <= NEAR_TIE_REL * z)
+        far = (hit & (z >= zf * (1 - NEAR_TIE_REL))) | (~hit & (z2 <= zf * (1 + NEAR_TIE_REL)))
+        r = rays(cam, rend["pixels"])
+        n = rend["nrm"]
+        cosang = np.abs((n * r).sum(-1)) / (np.linalg.norm(n, axis=-1) * np.linalg.norm(r, axis=-1))
+        graz = hit & ~(cosang >= GRAZING_COS)
+    return dict(near_tie=near, far_tie=far, grazing=graz)
+
+
+# --------------------------------------------------------------------------
+# Table I and E(X) (Sec. IV-B); E_soft, gradient and Gauss-Newton blocks
+# --------------------------------------------------------------------------
+
+def table1(c_r, c_s, dz, eps):
+    """Per-pixel Table I value s in {-1, 0, +1} and cell index (CELL_NAMES)."""
+    c_r = np.asarray(c_r); c_s = np.asarray(c_s); dz = np.asarray(dz, dtype=np.float64)
+    s = np.zeros(dz.shape, np.int64)
+    cell = np.full(dz.shape, 8, np.int64)
+    with np.errstate(invalid="ignore"):
+        ff = (c_r == FO) & (c_s == FO)
+        fu = (c_r == FO) & (c_s == FU)
+        uf = (c_r == FU) & (c_s == FO)
+        pen_ff = np.abs(dz) > eps          # |dz| > eps penalize, |dz| <= eps reward
+        pen_fu = dz <= 0                   # penalize if dz <= 0, reward if dz > 0
+        pen_uf = dz > 0                    # penalize if dz > 0, reward if dz <= 0
+    for m, pen, base in ((ff, pen_ff, 0), (fu, pen_fu, 2), (uf, pen_uf, 4)):
+        s[m] = np.where(pen[m], 1, -1)
+        cell[m] = base + pen[m].astype(np.int64)
+    scan_na = (c_s == NONE) | (c_s == UO)
+    map_na = ~scan_na & ((c_r == NONE) | (c_r == UO))
+    cell[scan_na] = 6
+    cell[map_na] = 7
+    return s, cell
+
+
+def residual(c_r, c_s, dz):
+    """E_soft residual r_p, the mask of scored cells and the active mask."""
+    ff = (c_r == FO) & (c_s == FO)
+    fu = (c_r == FO) & (c_s == FU)
+    uf = (c_r == FU) & (c_s == FO)
+    with np.errstate(invalid="ignore"):
+        r = np.where(ff, dz, np.where(fu, np.minimum(dz, 0.0), np.where(uf, np.maximum(dz, 0.0), 0.0)))
+        moving = ff | (fu & (dz < 0)) | (uf & (dz > 0))
+    scored = ff | fu | uf
+    return np.where(scored, r, 0.0), scored, moving
+
+
+def pixel_terms(rend, mesh_cls, scan_d, scan_c, cam, eps):
+    """Per-pixel Table I value, E_soft term, residual and Jacobian."""
+    pix = rend["pixels"]
+    hit = rend["id"] >= 0
+    c_r = np.where(hit, np.asarray(mesh_cls)[np.maximum(rend["id"], 0)], NONE)
+    d_r = rend["z"]
+    d_s = np.asarray(scan_d, np.float64).reshape(-1)[pix]
+    c_s = np.asarray(scan_c).reshape(-1)[pix]
+    with np.errstate(invalid="ignore"):
+        dz = d_r - d_s
+    s, cell = table1(c_r, c_s, dz, eps)
+    r, scored, moving = residual(c_r, c_s, dz)
+    rho = np.where(scored, 2.0 * np.minimum(r * r / (eps * eps), 1.0) - 1.0, 0.0)
+    active = scored & moving & (r * r < eps * eps)
+    ray = rays(cam, pix)
+    n = np.where(hit[:, None], rend["nrm"], 0.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ndr = (n * ray).sum(-1)
+        P = np.where(hit, d_r, 0.0)[:, None] * ray
+        J = np.concatenate([-n, np.cross(n, P)], -1) / ndr[:, None]
+    J = np.where(active[:, None], J, 0.0)
+    return dict(s=s, cell=cell, rho=rho, r=r, active=active, J=J, dz=dz, c_r=c_r, c_s=c_s,
+                d_r=d_r, d_s=d_s)
+
+
+def threshold_ties(terms, eps):
+    """Pixels whose Table I decision lies within the depth tolerance of a threshold."""
+    with np.errstate(invalid="ignore"):
+        scale = DEPTH_REL * np.fmax(np.abs(terms["d_r"]), np.abs(terms["d_s"]))
+        dz = terms["dz"]
+        ff = (terms["c_r"] == FO) & (terms["c_s"] == FO)
+        one = ((terms["c_r"] == FO) & (terms["c_s"] == FU)) | ((terms["c_r"] == FU) & (terms["c_s"] == FO))
+        return (ff & (np.abs(np.abs(dz) - eps) <= scale)) | (one & (np.abs(dz) <= scale))
+
+
+def reduce_terms(terms, mask=None):
+    """E_table, E_soft, 9 cell counts, gradient, J^T r, J^T J, n_active."""
+    m = np.ones(terms["s"].shape, bool) if mask is None else np.asarray(mask, bool)
+    J = terms["J"][m]
+    r = terms["r"][m]
+    act = terms["active"][m]
+    b = (r[act, None] * J[act]).sum(0)
+    H = J[act].T @ J[act]
+    return dict(e_table=int(terms["s"][m].sum()), e_soft=float(terms["rho"][m].sum()),
+                counts=np.bincount(terms["cell"][m], minlength=9), jtr=b, jtj=H,
+                n_active=int(act.sum()))
+
+
+def align_cost(mesh, cam, T_wc, scan_d, scan_c, eps=0.1, pixels=None, mode="contract"):
+    """Cost, gradient and Gauss-Newton blocks of one pose (FP64)."""
+    rend = render(mesh, cam, T_wc, pixels, mode)
+    terms = pixel_terms(rend, mesh[2], scan_d, scan_c, cam, eps)
+    out = reduce_terms(terms)
+    out["grad"] = (4.0 / (eps * eps)) * out["jtr"]
+    out["terms"] = terms
+    out["render"] = rend
+    return out
+
+
+# --------------------------------------------------------------------------
+# SE(3)
+# --------------------------------------------------------------------------
+
+def _hat(w):
+    return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+
+
+def se3_exp(delta):
+    """4x4 exp of delta = (upsilon, omega) (Rodrigues rotation, V-matrix translation)."""
+    v = np.asarray(delta[:3], np.float64); w = np.asarray(delta[3:], np.float64)
+    th = float(np.linalg.norm(w))
+    K = _hat(w)
+    if th < 1e-8:
+        A, B, C = 1.0 - th * th / 6.0, 0.5 - th * th / 24.0, 1.0 / 6.0 - th * th / 120.0
+    else:
+        A, B, C = np.sin(th) / th, (1.0 - np.cos(th)) / th ** 2, (th - np.sin(th)) / th ** 3
+    R = np.eye(3) + A * K + B * (K @ K)
+    V = np.eye(3) + B * K + C * (K @ K)
+    out = np.eye(4)
+    out[:3, :3] = R
+    out[:3, 3] = V @ v
+    return out
+
+
+def retract(T_wc, delta):
+    """T_wc * exp(delta) as a 3x4 matrix."""
+    T = np.vstack([np.asarray(T_wc, np.float64).reshape(3, 4), [0, 0, 0, 1]])
+    return (T @ se3_exp(delta))[:3]
+
+
+def gn_step(out, lam=0.0):
+    """Levenberg-Marquardt increment delta = -(H + lam diag H)^-1 b."""
+    H = out["jtj"]
+    A = H + lam * np.diag(np.diag(H))
+    return -np.linalg.solve(A, out["jtr"])
+
+
+def fd_jacobian(mesh, cam, T_wc, pixels, h=1e-4, mode="contract"):
+    """Central finite differences of the rendered depth with respect to the six
+    components of delta.  Returns (fd [N,6], stable [N] mask of pixels whose
+    winning triangle is the same at -h, 0 and +h on every axis)."""
+    base = render(mesh, cam, T_wc, pixels, mode)
+    fd = np.zeros((len(pixels), 6))
+    stable = base["id"] >= 0
+    for k in range(6):
+        e = np.zeros(6); e[k] = h
+        rp = render(mesh, cam, retract(T_wc, e), pixels, mode)
+        rm = render(mesh, cam, retract(T_wc, -e), pixels, mode)
+        fd[:, k] = (rp["z"] - rm["z"]) / (2 * h)
+        stable &= (rp["id"] == base["id"]) & (rm["id"] == base["id"])
+    return fd, stable, base

@@ -1,0 +1,111 @@
+"""The five seeded synthetic workloads of the pose-scoring path.
+
+The paper evaluates on an RGB-D office sequence (its Section VI), which is not
+available here; these synthetic scenes stand in for it with the same sensor
+shape (Kinect-like 640x480 z-depth), indoor room scale, and the inter-scan
+displacement the paper reports (about 0.15 m).  Every array is seeded.
+
+A workload whose map is the union of meshified range images (kinect,
+differentiation) carries the *range images and meshing parameters*; the
+consumer meshifies them (the oracle in tests, the GPU library in the bench),
+because meshification is part of the method and does not live here.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import scenes as S
+
+
+@dataclass
+class Workload:
+    name: str
+    cam: S.Camera
+    scene: S.Scene
+    T_true: np.ndarray                 # [3,4] ground-truth pose of the query scan
+    scan_depth: np.ndarray             # [H,W] f32 range image of the query scan
+    poses: np.ndarray                  # [B,3,4] candidate poses
+    z_min: float = 0.5
+    z_max: float = 8.0
+    eps: float = 0.1
+    map_mesh: tuple | None = None      # (xyz, tri, cls) when the map is procedural
+    views: list = field(default_factory=list)        # [T_wc] of meshified map views
+    view_depths: list = field(default_factory=list)  # [H,W] f32 range images
+    stride: int = 1
+    max_edge: float = 0.1
+
+
+def _room_center(scene):
+    return 0.5 * (scene.room_lo + scene.room_hi)
+
+
+def tiny(seed: int = 0) -> Workload:
+    """64x48 camera in a 4x4x2.5 m room with 8 boxes, procedural mesh of
+    2,304 wall triangles (0.25 m grid) + 96 box triangles; one candidate
+    pose 5 cm / 2 degrees from the truth."""
+    rng = np.random.default_rng(seed)
+    scene = S.random_box_room(seed, (4.0, 4.0, 2.5), 8)
+    mesh = S.triangulate_scene(scene, cell=0.25)
+    c = _room_center(scene)
+    T = S.look_pose(np.array([c[0], c[1], 1.2]), rng.uniform(0, 2 * np.pi), 0.0)
+    depth = S.range_image(scene, S.TINY, T, seed + 100, noise_rel=0.01)
+    cand = S.perturb(T, rng, 0.05, np.deg2rad(2.0), fixed=True)
+    return Workload("tiny", S.TINY, scene, T, depth, cand[None], map_mesh=mesh)
+
+
+def _meshified_room(seed, n_views, stride, cam, dropout=0.02, size=(6.0, 5.0, 2.8), n_boxes=16):
+    door = S.Door(axis=0, side=1, lo=(1.5, 0.0), hi=(2.5, 2.1))
+    scene = S.random_box_room(seed, size, n_boxes, doors=[door])
+    c = _room_center(scene)
+    views = S.circle_views(seed + 7, c, n_views)
+    depths = [S.range_image(scene, cam, T, seed * 1000 + k, noise_rel=0.01, dropout=dropout)
+              for k, T in enumerate(views)]
+    return scene, views, depths
+
+
+def _held_out_pose(scene, seed):
+    rng = np.random.default_rng(seed)
+    c = _room_center(scene)
+    ang = rng.uniform(0, 2 * np.pi)
+    pos = np.array([c[0] + np.cos(ang), c[1] + np.sin(ang), rng.uniform(1.2, 1.6)])
+    return S.look_pose(pos, ang + rng.uniform(-0.3, 0.3), rng.uniform(-0.2, 0.2)), rng
+
+
+def kinect(seed: int = 1, n_poses: int = 64) -> Workload:
+    """640x480 Kinect-like camera; map = 20 meshified views at stride 8
+    (about 186k triangles, free-occupied plus free-unknown); 64 candidates
+    drawn N(0, 3 cm) / N(0, 1.5 deg) per axis around the held-out truth."""
+    cam = S.KINECT
+    scene, views, depths = _meshified_room(seed, 20, 8, cam)
+    T, rng = _held_out_pose(scene, seed + 11)
+    depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.01, dropout=0.02)
+    poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n_poses)])
+    return Workload("kinect", cam, scene, T, depth, poses, views=views, view_depths=depths,
+                    stride=8, max_edge=0.1 * 8 / 2)
+
+
+def differentiation(seed: int = 1, n_poses: int = 64) -> Workload:
+    """640x480; map = 27 meshified views at stride 4 (27 x 37,842 =
+    1,021,734 triangles); 64 candidates exactly 10 cm / 5 deg from the truth."""
+    cam = S.KINECT
+    scene, views, depths = _meshified_room(seed, 27, 4, cam)
+    T, rng = _held_out_pose(scene, seed + 11)
+    depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.01, dropout=0.02)
+    poses = np.stack([S.perturb(T, rng, 0.10, np.deg2rad(5.0), fixed=True) for _ in range(n_poses)])
+    return Workload("differentiation", cam, scene, T, depth, poses, views=views,
+                    view_depths=depths, stride=4, max_edge=0.1 * 4 / 2)
+
+
+def wide(seed: int = 4, n_poses: int = 256, cell=0.018) -> Workload:
+    """1280x960 camera in a 60 m corridor with clutter, procedural mesh on a
+    ~1.8 cm grid (about 4M triangles); 10% dead pixels; 256 candidates."""
+    cam = S.WIDE
+    scene = S.corridor_scene(seed)
+    mesh = S.triangulate_scene(scene, cell=cell, box_cells=8)
+    rng = np.random.default_rng(seed)
+    T = S.look_pose(np.array([5.0, 1.25, 1.4]), 0.0 + rng.uniform(-0.2, 0.2), rng.uniform(-0.1, 0.1))
+    depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.01, dead=0.10)
+    poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n_poses)])
+    return Workload("wide", cam, scene, T, depth, poses, map_mesh=mesh)
