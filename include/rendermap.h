@@ -1,0 +1,275 @@
+/*
+ * rendermap.h -- C ABI of the MI355X (gfx950) pose-scoring library for
+ * RenderMap (Ryde & Ding, "RenderMap: Exploiting the Link Between Perception
+ * and Rendering for Dense Mapping", arXiv 1702.06813).
+ *
+ * The library evaluates E(X) = C(R(T(X)), Z_s) of Eq. (1) for many candidate
+ * poses X at once: it rasterizes the interface mesh (Sec. IV-A) into a
+ * z-buffer from each pose, compares every pixel with the scan image through
+ * Table I (Sec. IV-B), and reduces to the per-pose cost.  It also returns a
+ * continuous surrogate cost E_soft with its se(3) gradient and Gauss-Newton
+ * blocks, and runs the pose update of an optimizer step on the device.
+ *
+ * General rules (every entry point):
+ *   - Return RM_OK (0) or a negative rm_status; on error rm_last_error(ctx)
+ *     describes it.  No C++ exception crosses this boundary.
+ *   - Pointers documented "device" must point to memory on the context's
+ *     device; "host" pointers are read before the call returns.  The caller
+ *     owns every buffer; the library owns only the scratch inside rm_ctx and
+ *     keeps no caller pointer after a call returns.
+ *   - Work is enqueued asynchronously on the context stream (rm_ctx_set_stream)
+ *     and no call synchronizes, except rm_mesh_from_range (it returns counts).
+ *   - Arguments are validated on the host before anything is launched;
+ *     invalid arguments return RM_ERR_INVALID_ARG and launch nothing.
+ *   - Device arrays are dense and row-major.  Images are [H][W] with pixel
+ *     (u, v) at index v * W + u, its centre at continuous coordinates (u, v).
+ *   - Camera axes: x right, y down, z forward.  Depth is the perpendicular
+ *     distance from the camera plane (camera-frame z), as the paper's z-buffer
+ *     holds (Sec. V).
+ *   - A pose T_wc is 12 doubles, the row-major 3x4 matrix [R | t] mapping
+ *     camera coordinates to world (map) coordinates: the sensor pose X of
+ *     Eq. (1) in the map frame.
+ */
+#ifndef RENDERMAP_H
+#define RENDERMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RM_ABI_VERSION 1
+
+typedef enum {
+    RM_OK = 0,
+    RM_ERR_INVALID_ARG = -1,   /* bad pointer, size, count or parameter */
+    RM_ERR_OOM = -2,           /* device scratch could not be allocated */
+    RM_ERR_DEVICE = -3,        /* a HIP runtime call failed */
+    RM_ERR_CAPACITY = -4,      /* output capacity too small, or scratch must grow during graph capture */
+    RM_ERR_UNSUPPORTED = -5    /* valid request this build does not support */
+} rm_status;
+
+/* Interface classes of Sec. IV-A (free-occupied, free-unknown,
+ * unknown-occupied) and "no surface / NaN". */
+typedef enum { RM_FO = 0, RM_FU = 1, RM_UO = 2, RM_NONE = 3 } rm_class;
+
+typedef struct rm_ctx rm_ctx;
+
+/* Pinhole camera.  Pixel centres at integer (u, v); u = fx x/z + cx.
+ * Surfaces nearer than z_near are clipped, farther than z_far ignored. */
+typedef struct {
+    float fx, fy, cx, cy;
+    int32_t width, height;     /* 1 .. 4096 each */
+    float z_near, z_far;       /* 0 < z_near < z_far */
+} rm_camera;
+
+/* Interface mesh (Sec. IV-A): world-frame vertices and triangles, each with
+ * its interface class.  Triangles are grouped into clusters of
+ * RM_CLUSTER_TRIS consecutive triangles for culling; meshes whose consecutive
+ * triangles are spatial neighbours (as rm_mesh_from_range emits them) cull best. */
+typedef struct {
+    const float* xyz;          /* device [n_vertices][3] f32 */
+    int64_t n_vertices;
+    const int32_t* tri;        /* device [n_tris][3] i32 vertex indices */
+    const uint8_t* cls;        /* device [n_tris] u8, rm_class */
+    int64_t n_tris;            /* 0 .. 2^31 - 1 */
+    const void* clusters;      /* device, nullable: prepared buffer from rm_mesh_clusters
+                                  (cluster bounds, normals); NULL recomputes it every call */
+} rm_mesh;
+
+#define RM_CLUSTER_TRIS 256
+
+/* Scan image Z_s (Sec. IV-B): per pixel depth d_s and class c_s, as produced
+ * by rm_scan_image. */
+typedef struct {
+    const float* depth;        /* device [H][W] f32 d_s, NaN = dead pixel */
+    const uint8_t* cls;        /* device [H][W] u8 c_s (RM_FO, RM_FU or RM_NONE) */
+    const uint8_t* mask;       /* device [H][W] u8, nullable: pixels with 0 are left out of every sum */
+    rm_camera cam;             /* H = cam.height, W = cam.width */
+} rm_scan;
+
+/* Cost parameters.  eps is the inlier/outlier threshold of Table I
+ * (0.1 m in the paper); flags must be 0. */
+typedef struct {
+    float eps;
+    int32_t flags;
+} rm_cost_params;
+
+/* Per-pose result record: RM_OUT_STRIDE doubles per pose.
+ *   E_TABLE    E(X) = sum over pixels of the Table I value (+1/-1/0); exact
+ *   E_SOFT     sum over pixels of rho_p = 2 min(r_p^2/eps^2, 1) - 1 on scored
+ *              cells, 0 elsewhere, with r_p = dz (map FO / scan FO),
+ *              min(dz, 0) (FO / FU), max(dz, 0) (FU / FO), dz = d(p_r) - d(p_s)
+ *   COUNTS     9 pixel counts: FO/FO reward, FO/FO penalty, FO/FU reward,
+ *              FO/FU penalty, FU/FO reward, FU/FO penalty, ignored because the
+ *              scan pixel is NaN, ignored because the map pixel is NaN or UO,
+ *              ignored FU/FU
+ *   N_ACTIVE   pixels whose residual moves with the pose and |r_p| < eps
+ *   GRAD       d E_soft / d delta for T_wc exp(delta), delta = (v, w)
+ *   JTR        b = sum over active pixels of r_p J_p
+ *   JTJ        H = sum over active pixels of J_p^T J_p, upper triangle
+ *              row-major (21 values)
+ *   N_VISIBLE  triangles in clusters that survived frustum culling
+ * GRAD/JTR/JTJ/N_ACTIVE are written by rm_align_cost_grad only (zero from
+ * rm_align_cost).  J_p = [-n ; n x P] / (n . r) is the derivative of the
+ * rendered depth at pixel p, n the winning triangle's camera-frame normal,
+ * r = ((u - cx)/fx, (v - cy)/fy, 1), P = d(p_r) r. */
+enum {
+    RM_OUT_E_TABLE = 0,
+    RM_OUT_E_SOFT = 1,
+    RM_OUT_COUNTS = 2,
+    RM_OUT_N_ACTIVE = 11,
+    RM_OUT_GRAD = 12,
+    RM_OUT_JTR = 18,
+    RM_OUT_JTJ = 24,
+    RM_OUT_N_VISIBLE = 45,
+    RM_OUT_STRIDE = 48
+};
+
+/* Maximum number of scans per rm_align_cost / rm_align_cost_grad call. */
+#define RM_MAX_SCANS 32
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`, using the null stream until
+ * rm_ctx_set_stream.  *out receives the handle. */
+int rm_ctx_create(int32_t device, rm_ctx** out);
+/* Frees the context and its scratch.  NULL is accepted. */
+int rm_ctx_destroy(rm_ctx* ctx);
+/* Stream (a hipStream_t, or NULL for the null stream) on which later calls
+ * enqueue their work.  Must belong to the context's device. */
+int rm_ctx_set_stream(rm_ctx* ctx, void* stream);
+/* Message of the last failed call on this context ("" if none).  The string
+ * stays valid until the next call on the same context; NULL ctx gives the
+ * message of the last failed rm_ctx_create or NULL-context call. */
+const char* rm_last_error(const rm_ctx* ctx);
+/* Selects the screen-tile shape of the rasterizer: tile_w x tile_h one of
+ * 16x16, 32x32, 64x32; (0, 0) restores automatic choice (autotuned when
+ * rm_autotune is on, 32x32 otherwise).  Results do not depend on it. */
+int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
+/* Turns the tile autotuner on or off.  When on, the first call for a new
+ * (image size, pose count, triangle count) times every tile shape on the
+ * call's own inputs and keeps the fastest for later calls of that shape. */
+int rm_autotune(rm_ctx* ctx, int32_t enable);
+/* Current tile choice for a shape (after autotuning), for reporting. */
+int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int64_t n_tris,
+                int32_t* tile_w, int32_t* tile_h);
+
+/* Kernel timing for reports.  While enabled, every launch of the tile
+ * rasterizer (the kernel that rasterizes, compares and reduces) is bracketed
+ * by HIP events on the context stream; launches recorded into a stream
+ * capture are not timed.  rm_profile_read synchronizes the context stream,
+ * returns the number of timed launches and their summed duration in
+ * milliseconds, and clears the record. */
+int rm_profile(rm_ctx* ctx, int32_t enable);
+int rm_profile_read(rm_ctx* ctx, int64_t* n_launches, double* total_ms);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Begins stream capture on the context stream (hipStreamCaptureModeThreadLocal);
+ * every call until rm_graph_end is recorded instead of run.  Scratch must
+ * already be large enough: run each captured call once beforehand. */
+int rm_graph_begin(rm_ctx* ctx);
+/* Ends capture and instantiates the graph; *graph_exec receives a
+ * hipGraphExec_t owned by the caller (free with rm_graph_destroy). */
+int rm_graph_end(rm_ctx* ctx, void** graph_exec);
+/* Launches an instantiated graph on the context stream. */
+int rm_graph_launch(rm_ctx* ctx, void* graph_exec);
+int rm_graph_destroy(void* graph_exec);
+
+/* ---------------------------------------------------------------- scans and meshes */
+
+/* Scan image Z_s of a range image (Sec. IV-A/IV-B).  Per pixel of `depth`
+ * (device [H][W] f32, metres of z-depth):
+ *   NaN, negative, or in (0, z_min)       -> dead:      d = NaN,   c = RM_NONE
+ *   0, +inf, or > z_max (no return)       -> free to the sensor maximum:
+ *                                                       d = z_max, c = RM_FU
+ *   otherwise                             -> d = depth, c = RM_FO
+ * d_out (device [H][W] f32) and c_out (device [H][W] u8) are written. */
+int rm_scan_image(rm_ctx* ctx, const float* depth, int32_t height, int32_t width,
+                  float z_min, float z_max, float* d_out, uint8_t* c_out);
+
+/* Meshification of one range image (Sec. IV-A).  Grid nodes are the pixels
+ * (j*stride, i*stride), i < ceil(H/stride), j < ceil(W/stride); a node is
+ * classified as in rm_scan_image, back-projected at its depth (z_max for a
+ * no-return) through `cam` and moved to the world by T_wc (host, 12 doubles),
+ * in FP64, then rounded to f32.  Vertex i*gw + j belongs to node (i, j)
+ * (gw = ceil(W/stride)); dead nodes get an unreferenced NaN vertex.  The quad
+ * between nodes (i,j), (i,j+1), (i+1,j), (i+1,j+1) is dropped if a corner is
+ * dead, is RM_FU if a corner is a no-return or one of its four sides is
+ * longer than max_edge metres, RM_FO otherwise, and gives the triangles
+ * (00, 01, 11) and (00, 11, 10).  Quads are emitted in 8x8 blocks (blocks
+ * row-major, quads row-major inside a block).
+ *   xyz_out  device [gh*gw][3] f32 (gh = ceil(H/stride))
+ *   tri_out  device [cap_t][3] i32,  cls_out device [cap_t] u8
+ *   n_v_out, n_t_out  host; receive gh*gw and the triangle count.
+ * Synchronizes the context stream to read the count back.  If more than
+ * cap_t triangles result, returns RM_ERR_CAPACITY (n_t_out holds the
+ * needed count; the outputs are unspecified). */
+int rm_mesh_from_range(rm_ctx* ctx, const float* depth, rm_camera cam, const double* T_wc,
+                       int32_t stride, float z_min, float z_max, float max_edge,
+                       float* xyz_out, int32_t* tri_out, uint8_t* cls_out, int64_t cap_t,
+                       int64_t* n_v_out, int64_t* n_t_out);
+
+/* Bytes of the prepared-mesh buffer for a mesh of n_tris triangles: one
+ * 32-byte world AABB record per cluster of RM_CLUSTER_TRIS consecutive
+ * triangles (padded to a multiple of 256 bytes), then the world-frame unit
+ * normal of every triangle ([n_tris][3] f32, from the FP32 vertices in FP64). */
+int64_t rm_mesh_clusters_size(int64_t n_tris);
+/* Writes the prepared-mesh buffer of `mesh` into `out` (device,
+ * rm_mesh_clusters_size bytes).  Point rm_mesh.clusters at it to skip the
+ * per-call recomputation; recompute after changing the mesh. */
+int rm_mesh_clusters(rm_ctx* ctx, const rm_mesh* mesh, void* out);
+
+/* ---------------------------------------------------------------- z-buffer */
+
+/* Renders R(T(X)) of Eq. (1) for B poses.  T_wc: device [B][12] f64.
+ * Outputs (device, each nullable):
+ *   depth_out [B][H][W] f32: depth of the nearest surface, NaN where none
+ *   tri_out   [B][H][W] i32: its triangle id, -1 where none
+ *   cls_out   [B][H][W] u8 : its rm_class, RM_NONE where none
+ * Coverage follows the rasterization contract: float32 camera transform
+ * R32 = fl32(R^T), d = fl32(Xw - t) (difference in FP64), Xc = R32 d with
+ * fmaf in the order z-, y-, x-column; clip at z >= z_near interpolating from
+ * the inside vertex; u = fmaf(fx Xc.x, 1/Xc.z, cx) (v alike); snap to
+ * rint(256 u), rint(256 v); integer edge functions with the top-left rule
+ * (y down).  The nearest surface is the minimum of (depth, triangle id). */
+int rm_render_depth(rm_ctx* ctx, const rm_mesh* mesh, rm_camera cam, const double* T_wc,
+                    int32_t n_poses, float* depth_out, int32_t* tri_out, uint8_t* cls_out);
+
+/* ---------------------------------------------------------------- cost */
+
+/* E(X) of Eq. (1) and Table I for every pose of S scans at once.
+ * scans: host [S] (device pointers inside), 1 <= S <= RM_MAX_SCANS.
+ * pose_off: host [S+1] non-decreasing offsets, pose_off[0] = 0; poses
+ *   pose_off[s] .. pose_off[s+1]-1 are scored against scan s.
+ * T_wc: device [P][12] f64, P = pose_off[S].
+ * out: device [P][RM_OUT_STRIDE] f64, fully overwritten (see RM_OUT_*). */
+int rm_align_cost(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
+                  const int32_t* pose_off, const double* T_wc, rm_cost_params params,
+                  double* out);
+/* As rm_align_cost, also writing GRAD, JTR, JTJ and N_ACTIVE. */
+int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
+                       const int32_t* pose_off, const double* T_wc, rm_cost_params params,
+                       double* out);
+
+/* ---------------------------------------------------------------- optimizer step */
+
+/* Levenberg-Marquardt pose update for P poses from their result records:
+ *   delta = -(H + lambda diag(H))^-1 b,   T_wc <- T_wc exp(delta)
+ * (H = JTJ, b = JTR; delta = 0 where H + lambda diag(H) is not positive
+ * definite).  T_wc: device [P][12] f64, updated in place; delta_out: device
+ * [P][6] f64, nullable. */
+int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda,
+               double* T_wc, double* delta_out);
+/* T_out = T_in exp(delta) for P poses (device [P][12], [P][6], [P][12] f64;
+ * T_out may equal T_in). */
+int rm_se3_retract(rm_ctx* ctx, const double* T_in, const double* delta, int32_t n_poses,
+                   double* T_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RENDERMAP_H */

@@ -1,0 +1,565 @@
+// Host runtime of the rendermap C ABI: context, argument validation, scratch
+// arena, batch descriptors, tile autotuner and stream capture helpers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "rm_internal.h"
+
+using namespace rm;
+
+struct rm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_size = 0;
+    int32_t* pinned = nullptr;        // small host readback buffer
+    std::string err;
+    int tile_w = 0, tile_h = 0;       // 0 = automatic
+    bool autotune = false;
+    std::map<std::tuple<int, int, int, int64_t, int>, std::pair<int, int>> tuned;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    size_t prof_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(rm_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf; else g_err = buf;
+    return code;
+}
+
+#define RM_HIP(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, RM_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool capturing(rm_ctx* ctx) {
+    hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &s) != hipSuccess) return false;
+    return s != hipStreamCaptureStatusNone;
+}
+
+// Bump allocator over the context scratch; sizes first, then carve.
+struct Carve {
+    size_t off = 0;
+    template <typename T>
+    size_t take(int64_t n) {
+        const size_t o = off;
+        off += ((size_t)std::max<int64_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+int ensure_scratch(rm_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->scratch_size) return RM_OK;
+    if (capturing(ctx))
+        return fail(ctx, RM_ERR_CAPACITY, "scratch must grow to %zu bytes during stream capture; "
+                                          "run the call once before capturing", bytes);
+    RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->scratch) RM_HIP(ctx, hipFree(ctx->scratch));
+    ctx->scratch = nullptr;
+    ctx->scratch_size = 0;
+    const size_t sz = std::max(bytes + bytes / 4, (size_t)1 << 20);
+    if (hipMalloc(&ctx->scratch, sz) != hipSuccess) {
+        ctx->scratch = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, RM_ERR_OOM, "could not allocate %zu bytes of scratch", sz);
+    }
+    ctx->scratch_size = sz;
+    return RM_OK;
+}
+
+template <typename T>
+T* at(rm_ctx* ctx, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ctx->scratch) + off); }
+
+int check_camera(rm_ctx* ctx, const rm_camera& c) {
+    if (c.width < 1 || c.height < 1 || c.width > 4096 || c.height > 4096)
+        return fail(ctx, RM_ERR_INVALID_ARG, "image size %dx%d outside 1..4096", c.width, c.height);
+    if (!(std::isfinite(c.fx) && std::isfinite(c.fy) && c.fx != 0.0f && c.fy != 0.0f &&
+          std::isfinite(c.cx) && std::isfinite(c.cy)))
+        return fail(ctx, RM_ERR_INVALID_ARG, "camera intrinsics must be finite with fx, fy != 0");
+    if (std::fabs(c.cx) > 8192.0f || std::fabs(c.cy) > 8192.0f)
+        return fail(ctx, RM_ERR_INVALID_ARG, "principal point beyond 8192 px");
+    if (!(c.z_near > 0.0f && c.z_far > c.z_near && std::isfinite(c.z_far)))
+        return fail(ctx, RM_ERR_INVALID_ARG, "need 0 < z_near < z_far < inf (got %g, %g)", c.z_near, c.z_far);
+    return RM_OK;
+}
+
+int check_mesh(rm_ctx* ctx, const rm_mesh* m) {
+    if (!m) return fail(ctx, RM_ERR_INVALID_ARG, "mesh is NULL");
+    if (m->n_tris < 0 || m->n_tris >= ((int64_t)1 << 31) || m->n_vertices < 0 || m->n_vertices >= ((int64_t)1 << 31))
+        return fail(ctx, RM_ERR_INVALID_ARG, "mesh sizes out of range (V=%lld, T=%lld)",
+                    (long long)m->n_vertices, (long long)m->n_tris);
+    if (m->n_tris > 0 && (!m->xyz || !m->tri || !m->cls || m->n_vertices < 1))
+        return fail(ctx, RM_ERR_INVALID_ARG, "mesh arrays must be non-NULL and n_vertices >= 1 when n_tris > 0");
+    return RM_OK;
+}
+
+bool valid_tile(int w, int h) {
+    return (w == 16 && h == 16) || (w == 32 && h == 32) || (w == 64 && h == 32);
+}
+
+const int kTiles[3][2] = {{16, 16}, {32, 32}, {64, 32}};
+
+// Fills the scan descriptors and counts items and partial records.
+void plan(BatchDesc& bd, int tw, int th) {
+    bd.tile_w = tw;
+    bd.tile_h = th;
+    int64_t items = 0, recs = 0;
+    for (int s = 0; s < bd.n_scans; ++s) {
+        ScanDesc& d = bd.s[s];
+        d.tiles_x = (d.width + tw - 1) / tw;
+        d.tiles_y = (d.height + th - 1) / th;
+        d.item_off = items;
+        d.rec_off = recs;
+        const int64_t n = (int64_t)d.n_poses * d.tiles_x * d.tiles_y;
+        items += n;
+        recs += n;
+    }
+    bd.n_items = items;
+}
+
+int64_t total_records(const BatchDesc& bd) {
+    int64_t r = 0;
+    for (int s = 0; s < bd.n_scans; ++s) r += (int64_t)bd.s[s].n_poses * bd.s[s].tiles_x * bd.s[s].tiles_y;
+    return r;
+}
+
+// One scoring pass: cull, rasterize (+ fused comparison), reduce.
+int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
+             float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
+    plan(bd, tw, th);
+    const int P = bd.n_poses;
+    const int64_t C = (mesh->n_tris + kClusterTris - 1) / kClusterTris;
+    const int64_t R = total_records(bd);
+    Carve cv;
+    const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P);
+    const size_t o_vis = cv.take<uint2>((int64_t)P * C);
+    const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
+    const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
+    int rc = ensure_scratch(ctx, cv.off);
+    if (rc) return rc;
+    int32_t* vis_count = at<int32_t>(ctx, o_cnt);
+    int32_t* vis_tris = vis_count + P;
+    const void* prep = mesh->clusters;
+    if (!prep && C > 0) {
+        void* w = at<char>(ctx, o_cb);
+        RM_HIP(ctx, launch_prepare(ctx->stream, mesh->xyz, mesh->n_vertices, mesh->tri, mesh->n_tris, w));
+        prep = w;
+    }
+    const ClusterBounds* cb = static_cast<const ClusterBounds*>(prep);
+    const float* nrm = prep ? reinterpret_cast<const float*>(static_cast<const char*>(prep) +
+                                                             prepared_normals_offset(mesh->n_tris))
+                            : nullptr;
+    RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P));
+    uint2* vis = at<uint2>(ctx, o_vis);
+    RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
+    RasterArgs a;
+    a.xyz = mesh->xyz;
+    a.tri = mesh->tri;
+    a.cls = mesh->cls;
+    a.nrm = nrm;
+    a.n_tris = mesh->n_tris;
+    a.vmax = mesh->n_vertices > 0 ? (uint32_t)(mesh->n_vertices - 1) : 0u;
+    a.n_clusters = (int32_t)C;
+    a.T_wc = T_wc;
+    a.vis = vis;
+    a.vis_count = vis_count;
+    a.rec = at<float>(ctx, o_rec);
+    a.eps = eps;
+    a.depth_out = depth_out;
+    a.tri_out = tri_out;
+    a.cls_out = cls_out;
+    hipEvent_t pe1 = nullptr;
+    if (ctx->profiling && !capturing(ctx)) {
+        if (ctx->prof_used == ctx->prof_events.size()) {
+            hipEvent_t x, y;
+            RM_HIP(ctx, hipEventCreate(&x));
+            RM_HIP(ctx, hipEventCreate(&y));
+            ctx->prof_events.emplace_back(x, y);
+        }
+        RM_HIP(ctx, hipEventRecord(ctx->prof_events[ctx->prof_used].first, ctx->stream));
+        pe1 = ctx->prof_events[ctx->prof_used].second;
+        ++ctx->prof_used;
+    }
+    RM_HIP(ctx, launch_raster(ctx->stream, bd, a, mode));
+    if (pe1) RM_HIP(ctx, hipEventRecord(pe1, ctx->stream));
+    if (mode != kRender)
+        RM_HIP(ctx, launch_reduce(ctx->stream, bd, a.rec, vis_tris, eps, mode == kGrad, out));
+    return RM_OK;
+}
+
+// Chooses the tile shape (explicit, cached autotune result, or default) and runs.
+int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const double* T_wc, float eps,
+               double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
+    if (ctx->tile_w) return run_pass(ctx, mesh, bd, ctx->tile_w, ctx->tile_h, mode, T_wc, eps, out, depth_out,
+                                     tri_out, cls_out);
+    const auto key = std::make_tuple(bd.s[0].width, bd.s[0].height, bd.n_poses, mesh->n_tris, mode);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end())
+        return run_pass(ctx, mesh, bd, it->second.first, it->second.second, mode, T_wc, eps, out, depth_out,
+                        tri_out, cls_out);
+    if (!ctx->autotune || capturing(ctx))
+        return run_pass(ctx, mesh, bd, 32, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out);
+    if (!ctx->ev0) {
+        RM_HIP(ctx, hipEventCreate(&ctx->ev0));
+        RM_HIP(ctx, hipEventCreate(&ctx->ev1));
+    }
+    float best = 1e30f;
+    int bi = 1;
+    for (int k = 0; k < 3; ++k) {
+        // one warm-up and one timed pass per shape
+        for (int rep = 0; rep < 2; ++rep) {
+            if (rep == 1) RM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            int rc = run_pass(ctx, mesh, bd, kTiles[k][0], kTiles[k][1], mode, T_wc, eps, out, depth_out, tri_out,
+                              cls_out);
+            if (rc) return rc;
+        }
+        RM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+        RM_HIP(ctx, hipEventSynchronize(ctx->ev1));
+        float ms = 0.0f;
+        RM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        if (ms < best) { best = ms; bi = k; }
+    }
+    ctx->tuned[key] = {kTiles[bi][0], kTiles[bi][1]};
+    return run_pass(ctx, mesh, bd, kTiles[bi][0], kTiles[bi][1], mode, T_wc, eps, out, depth_out, tri_out, cls_out);
+}
+
+int fill_scan(rm_ctx* ctx, ScanDesc& d, const rm_camera& c) {
+    int rc = check_camera(ctx, c);
+    if (rc) return rc;
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    d.width = c.width; d.height = c.height;
+    d.z_near = c.z_near; d.z_far = c.z_far;
+    return RM_OK;
+}
+
+int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t S, const int32_t* pose_off,
+                 const double* T_wc, rm_cost_params params, double* out, int mode) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (!scans || !pose_off) return fail(ctx, RM_ERR_INVALID_ARG, "scans and pose_off must be non-NULL");
+    if (S < 1 || S > RM_MAX_SCANS) return fail(ctx, RM_ERR_INVALID_ARG, "n_scans %d outside 1..%d", S, RM_MAX_SCANS);
+    if (!(params.eps > 0.0f) || !std::isfinite(params.eps))
+        return fail(ctx, RM_ERR_INVALID_ARG, "eps must be positive and finite");
+    if (params.flags != 0) return fail(ctx, RM_ERR_INVALID_ARG, "flags must be 0");
+    if (pose_off[0] != 0) return fail(ctx, RM_ERR_INVALID_ARG, "pose_off[0] must be 0");
+    BatchDesc bd;
+    std::memset(&bd, 0, sizeof(bd));
+    bd.n_scans = S;
+    for (int s = 0; s < S; ++s) {
+        if (pose_off[s + 1] < pose_off[s]) return fail(ctx, RM_ERR_INVALID_ARG, "pose_off must be non-decreasing");
+        if (!scans[s].depth || !scans[s].cls)
+            return fail(ctx, RM_ERR_INVALID_ARG, "scan %d has NULL depth or cls", s);
+        rc = fill_scan(ctx, bd.s[s], scans[s].cam);
+        if (rc) return rc;
+        bd.s[s].depth = scans[s].depth;
+        bd.s[s].cls = scans[s].cls;
+        bd.s[s].mask = scans[s].mask;
+        bd.s[s].pose_off = pose_off[s];
+        bd.s[s].n_poses = pose_off[s + 1] - pose_off[s];
+    }
+    const int P = pose_off[S];
+    if (P > 65535) return fail(ctx, RM_ERR_INVALID_ARG, "at most 65535 poses per call (got %d)", P);
+    if (P == 0) return RM_OK;
+    if (!T_wc || !out) return fail(ctx, RM_ERR_INVALID_ARG, "T_wc and out must be non-NULL");
+    bd.n_poses = P;
+    DeviceGuard g(ctx->device);
+    return run_scored(ctx, mesh, bd, mode, T_wc, params.eps, out, nullptr, nullptr, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rm_ctx_create(int32_t device, rm_ctx** out) {
+    if (!out) return fail(nullptr, RM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, RM_ERR_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n) return fail(nullptr, RM_ERR_INVALID_ARG, "device %d outside 0..%d", device, n - 1);
+    rm_ctx* c = new rm_ctx();
+    c->device = device;
+    DeviceGuard g(device);
+    if (hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(nullptr, RM_ERR_DEVICE, "hipHostMalloc failed");
+    }
+    *out = c;
+    return RM_OK;
+}
+
+int rm_ctx_destroy(rm_ctx* ctx) {
+    if (!ctx) return RM_OK;
+    {
+        DeviceGuard g(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream); else (void)hipDeviceSynchronize();
+        if (ctx->scratch) (void)hipFree(ctx->scratch);
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+        if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+        for (auto& e : ctx->prof_events) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+    delete ctx;
+    return RM_OK;
+}
+
+int rm_ctx_set_stream(rm_ctx* ctx, void* stream) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return RM_OK;
+}
+
+const char* rm_last_error(const rm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    if (tile_w == 0 && tile_h == 0) { ctx->tile_w = ctx->tile_h = 0; return RM_OK; }
+    if (!valid_tile(tile_w, tile_h)) return fail(ctx, RM_ERR_INVALID_ARG, "tile %dx%d not supported", tile_w, tile_h);
+    ctx->tile_w = tile_w;
+    ctx->tile_h = tile_h;
+    return RM_OK;
+}
+
+int rm_autotune(rm_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->autotune = enable != 0;
+    return RM_OK;
+}
+
+int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int64_t n_tris, int32_t* tile_w,
+                int32_t* tile_h) {
+    if (!ctx || !tile_w || !tile_h) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    if (ctx->tile_w) { *tile_w = ctx->tile_w; *tile_h = ctx->tile_h; return RM_OK; }
+    for (int mode = kCost; mode <= kGrad; ++mode) {
+        auto it = ctx->tuned.find(std::make_tuple(width, height, n_poses, n_tris, mode));
+        if (it != ctx->tuned.end()) { *tile_w = it->second.first; *tile_h = it->second.second; return RM_OK; }
+    }
+    *tile_w = 32;
+    *tile_h = 32;
+    return RM_OK;
+}
+
+int rm_profile(rm_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->profiling = enable != 0;
+    return RM_OK;
+}
+
+int rm_profile_read(rm_ctx* ctx, int64_t* n_launches, double* total_ms) {
+    if (!ctx || !n_launches || !total_ms) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k < ctx->prof_used; ++k) {
+        float ms = 0.0f;
+        RM_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_events[k].first, ctx->prof_events[k].second));
+        tot += ms;
+    }
+    *n_launches = (int64_t)ctx->prof_used;
+    *total_ms = tot;
+    ctx->prof_used = 0;
+    return RM_OK;
+}
+
+int rm_graph_begin(rm_ctx* ctx) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    if (!ctx->stream) return fail(ctx, RM_ERR_INVALID_ARG, "capture needs a non-null stream");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    return RM_OK;
+}
+
+int rm_graph_end(rm_ctx* ctx, void** graph_exec) {
+    if (!ctx || !graph_exec) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard g(ctx->device);
+    hipGraph_t graph = nullptr;
+    RM_HIP(ctx, hipStreamEndCapture(ctx->stream, &graph));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(ctx, RM_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    *graph_exec = ex;
+    return RM_OK;
+}
+
+int rm_graph_launch(rm_ctx* ctx, void* graph_exec) {
+    if (!ctx || !graph_exec) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), ctx->stream));
+    return RM_OK;
+}
+
+int rm_graph_destroy(void* graph_exec) {
+    if (graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
+    return RM_OK;
+}
+
+int rm_scan_image(rm_ctx* ctx, const float* depth, int32_t height, int32_t width, float z_min, float z_max,
+                  float* d_out, uint8_t* c_out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (!depth || !d_out || !c_out) return fail(ctx, RM_ERR_INVALID_ARG, "NULL image pointer");
+    if (height < 1 || width < 1 || (int64_t)height * width > ((int64_t)1 << 26))
+        return fail(ctx, RM_ERR_INVALID_ARG, "bad image size %dx%d", width, height);
+    if (!(z_min >= 0.0f && z_max > z_min && std::isfinite(z_max)))
+        return fail(ctx, RM_ERR_INVALID_ARG, "need 0 <= z_min < z_max < inf");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_scan_image(ctx->stream, depth, height, width, z_min, z_max, d_out, c_out));
+    return RM_OK;
+}
+
+int rm_mesh_from_range(rm_ctx* ctx, const float* depth, rm_camera cam, const double* T_wc, int32_t stride,
+                       float z_min, float z_max, float max_edge, float* xyz_out, int32_t* tri_out,
+                       uint8_t* cls_out, int64_t cap_t, int64_t* n_v_out, int64_t* n_t_out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_camera(ctx, cam);
+    if (rc) return rc;
+    if (!depth || !T_wc || !xyz_out || !tri_out || !cls_out || !n_v_out || !n_t_out)
+        return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    if (stride < 1 || stride > 256) return fail(ctx, RM_ERR_INVALID_ARG, "stride %d outside 1..256", stride);
+    if (!(z_min >= 0.0f && z_max > z_min && std::isfinite(z_max)))
+        return fail(ctx, RM_ERR_INVALID_ARG, "need 0 <= z_min < z_max < inf");
+    if (!(max_edge > 0.0f)) return fail(ctx, RM_ERR_INVALID_ARG, "max_edge must be positive");
+    if (cap_t < 0) return fail(ctx, RM_ERR_INVALID_ARG, "cap_t must be >= 0");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(T_wc[k])) return fail(ctx, RM_ERR_INVALID_ARG, "pose has a non-finite entry");
+    if (capturing(ctx)) return fail(ctx, RM_ERR_UNSUPPORTED, "rm_mesh_from_range synchronizes; not capturable");
+    DeviceGuard g(ctx->device);
+    const int32_t gh = (cam.height + stride - 1) / stride, gw = (cam.width + stride - 1) / stride;
+    const int64_t nn = (int64_t)gh * gw;
+    const int64_t nb = meshify_blocks(cam.height, cam.width, stride);
+    Carve cv;
+    const size_t o_kind = cv.take<uint8_t>(nn);
+    const size_t o_cnt = cv.take<int32_t>(nb);
+    const size_t o_off = cv.take<int32_t>(nb);
+    const size_t o_tot = cv.take<int32_t>(1);
+    rc = ensure_scratch(ctx, cv.off);
+    if (rc) return rc;
+    RM_HIP(ctx, launch_meshify(ctx->stream, depth, cam, T_wc, stride, z_min, z_max, max_edge, xyz_out, tri_out,
+                               cls_out, cap_t, at<uint8_t>(ctx, o_kind), at<int32_t>(ctx, o_cnt),
+                               at<int32_t>(ctx, o_off), at<int32_t>(ctx, o_tot)));
+    RM_HIP(ctx, hipMemcpyAsync(ctx->pinned, at<int32_t>(ctx, o_tot), sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *n_v_out = nn;
+    *n_t_out = ctx->pinned[0];
+    if (ctx->pinned[0] > cap_t)
+        return fail(ctx, RM_ERR_CAPACITY, "mesh has %d triangles, capacity %lld", ctx->pinned[0], (long long)cap_t);
+    return RM_OK;
+}
+
+int64_t rm_mesh_clusters_size(int64_t n_tris) {
+    if (n_tris <= 0) return 0;
+    return prepared_normals_offset(n_tris) + n_tris * 3 * (int64_t)sizeof(float);
+}
+
+int rm_mesh_clusters(rm_ctx* ctx, const rm_mesh* mesh, void* out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (!out && mesh->n_tris > 0) return fail(ctx, RM_ERR_INVALID_ARG, "out is NULL");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_prepare(ctx->stream, mesh->xyz, mesh->n_vertices, mesh->tri, mesh->n_tris, out));
+    return RM_OK;
+}
+
+int rm_render_depth(rm_ctx* ctx, const rm_mesh* mesh, rm_camera cam, const double* T_wc, int32_t n_poses,
+                    float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (n_poses < 0 || n_poses > 65535) return fail(ctx, RM_ERR_INVALID_ARG, "n_poses %d outside 0..65535", n_poses);
+    if (n_poses == 0) return RM_OK;
+    if (!T_wc) return fail(ctx, RM_ERR_INVALID_ARG, "T_wc is NULL");
+    BatchDesc bd;
+    std::memset(&bd, 0, sizeof(bd));
+    bd.n_scans = 1;
+    bd.n_poses = n_poses;
+    rc = fill_scan(ctx, bd.s[0], cam);
+    if (rc) return rc;
+    bd.s[0].pose_off = 0;
+    bd.s[0].n_poses = n_poses;
+    DeviceGuard g(ctx->device);
+    const int tw = ctx->tile_w ? ctx->tile_w : 32, th = ctx->tile_w ? ctx->tile_h : 32;
+    return run_pass(ctx, mesh, bd, tw, th, kRender, T_wc, 1.0f, nullptr, depth_out, tri_out, cls_out);
+}
+
+int rm_align_cost(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans, const int32_t* pose_off,
+                  const double* T_wc, rm_cost_params params, double* out) {
+    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kCost);
+}
+
+int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
+                       const int32_t* pose_off, const double* T_wc, rm_cost_params params, double* out) {
+    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kGrad);
+}
+
+int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda, double* T_wc, double* delta_out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (n_poses < 0) return fail(ctx, RM_ERR_INVALID_ARG, "n_poses < 0");
+    if (n_poses == 0) return RM_OK;
+    if (!out || !T_wc) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ctx, RM_ERR_INVALID_ARG, "lambda must be >= 0");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_gn_step(ctx->stream, out, n_poses, lambda, T_wc, delta_out));
+    return RM_OK;
+}
+
+int rm_se3_retract(rm_ctx* ctx, const double* T_in, const double* delta, int32_t n_poses, double* T_out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (n_poses < 0) return fail(ctx, RM_ERR_INVALID_ARG, "n_poses < 0");
+    if (n_poses == 0) return RM_OK;
+    if (!T_in || !delta || !T_out) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_retract(ctx->stream, T_in, delta, n_poses, T_out));
+    return RM_OK;
+}
+
+}  // extern "C"

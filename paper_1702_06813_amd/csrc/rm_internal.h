@@ -1,0 +1,95 @@
+// Internal declarations of the rendermap library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rendermap.h"
+
+namespace rm {
+
+constexpr int kWG = 256;                 // threads per workgroup everywhere
+constexpr int kClusterTris = RM_CLUSTER_TRIS;
+constexpr int kQuadBlock = 8;            // meshify emits 8x8 blocks of quads
+constexpr int kRecFields = 40;           // per-(pose, tile) partial record, 4-byte fields
+constexpr int kSnapLimit = 1 << 29;      // |snapped coordinate| must stay below this
+
+// Per-cluster bounds written by rm_mesh_clusters: world AABB.
+struct ClusterBounds {
+    float lo[3];
+    float hi[3];
+    int32_t n_tris;       // triangles in this cluster (<= kClusterTris)
+    int32_t pad;
+};
+static_assert(sizeof(ClusterBounds) == 32, "cluster record layout");
+
+// One scan of a batched call, with its slice of poses and its tile grid.
+struct ScanDesc {
+    const float* depth;
+    const uint8_t* cls;
+    const uint8_t* mask;
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float z_near, z_far;
+    int32_t pose_off, n_poses;
+    int32_t tiles_x, tiles_y;
+    int64_t item_off;     // first work item of this scan
+    int64_t rec_off;      // first partial record of this scan
+};
+
+struct BatchDesc {
+    int32_t n_scans;
+    int32_t n_poses;
+    int32_t tile_w, tile_h;
+    int64_t n_items;
+    ScanDesc s[RM_MAX_SCANS];
+};
+
+enum Mode { kRender = 0, kCost = 1, kGrad = 2 };
+
+struct RasterArgs {
+    const float* xyz;
+    const int32_t* tri;
+    const uint8_t* cls;
+    const float* nrm;            // [T][3] world-frame unit normals (prepared mesh)
+    int64_t n_tris;
+    uint32_t vmax;               // n_vertices - 1: vertex indices are clamped to it
+    int32_t n_clusters;
+    const double* T_wc;          // [P][12]
+    const uint2* vis;            // [P][n_clusters] (cluster, packed tile rect)
+    const int32_t* vis_count;    // [P]
+    float* rec;                  // partial records [n_records][kRecFields]
+    float eps;
+    // render outputs
+    float* depth_out;
+    int32_t* tri_out;
+    uint8_t* cls_out;
+};
+
+// launchers (return hipError_t)
+hipError_t launch_scan_image(hipStream_t st, const float* depth, int32_t H, int32_t W, float z_min,
+                             float z_max, float* d_out, uint8_t* c_out);
+hipError_t launch_meshify(hipStream_t st, const float* depth, rm_camera cam, const double* T,
+                          int32_t stride, float z_min, float z_max, float max_edge, float* xyz,
+                          int32_t* tri, uint8_t* cls, int64_t cap_t, uint8_t* kind,
+                          int32_t* block_counts, int32_t* block_offsets, int32_t* total);
+// Prepared-mesh buffer: [n_clusters] ClusterBounds, then (256-byte aligned)
+// [n_tris][3] f32 unit normals.
+int64_t prepared_normals_offset(int64_t n_tris);
+hipError_t launch_prepare(hipStream_t st, const float* xyz, int64_t n_vertices, const int32_t* tri,
+                          int64_t n_tris, void* out);
+hipError_t launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
+hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds* cb,
+                       int32_t n_clusters, const double* T_wc, uint2* vis, int32_t* vis_count,
+                       int32_t* vis_tris);
+hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode);
+hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec,
+                         const int32_t* vis_tris, float eps, int grad, double* out);
+hipError_t launch_gn_step(hipStream_t st, const double* out, int32_t P, double lambda, double* T,
+                          double* delta_out);
+hipError_t launch_retract(hipStream_t st, const double* T_in, const double* delta, int32_t P,
+                          double* T_out);
+
+int64_t meshify_blocks(int32_t H, int32_t W, int32_t stride);
+
+}  // namespace rm

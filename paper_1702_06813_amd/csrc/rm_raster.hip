@@ -1,0 +1,608 @@
+// Pose scoring on gfx950: cluster frustum cull, screen-tile rasterization into
+// an LDS z-buffer of packed (depth | triangle id) keys resolved by 64-bit
+// atomic min, and the fused per-pixel comparison of Table I, the E_soft
+// residual and its se(3) Jacobian, reduced per tile and then per pose.
+//
+// The z-buffer R(T(X)) is Eq. (1) of the paper; the per-pixel rules are its
+// Table I (Sec. IV-B); the total error is their sum over pixels (Sec. IV-B).
+#include "rm_internal.h"
+
+namespace rm {
+
+namespace {
+
+// ------------------------------------------------------------------ pose data
+
+// World -> camera rotation rounded to f32 (R32[i][j] = fl32(R[j][i])) and the
+// FP64 camera centre; the float32 rasterization contract transforms a world
+// point as d = fl32(Xw - t) (difference in FP64), Xc = R32 d with explicit
+// fmaf in the order z-, y-, x-column.
+struct PoseF {
+    float R[3][3];
+    double Rd[3][3];      // world -> camera rotation in FP64 (depth planes)
+    double t[3];
+};
+
+__device__ __forceinline__ void load_pose(const double* __restrict__ T, PoseF& P) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            P.Rd[i][j] = T[4 * j + i];
+            P.R[i][j] = (float)T[4 * j + i];
+        }
+        P.t[i] = T[4 * i + 3];
+    }
+}
+
+__device__ __forceinline__ float3 cam_contract(const PoseF& P, float x, float y, float z) {
+    const float d0 = (float)((double)x - P.t[0]);
+    const float d1 = (float)((double)y - P.t[1]);
+    const float d2 = (float)((double)z - P.t[2]);
+    float3 c;
+    c.x = fmaf(P.R[0][2], d2, fmaf(P.R[0][1], d1, P.R[0][0] * d0));
+    c.y = fmaf(P.R[1][2], d2, fmaf(P.R[1][1], d1, P.R[1][0] * d0));
+    c.z = fmaf(P.R[2][2], d2, fmaf(P.R[2][1], d1, P.R[2][0] * d0));
+    return c;
+}
+
+struct CamF {
+    float fx, fy, cx, cy, zn, zf;
+    int W, H;
+};
+
+// Near-plane clip point, interpolated from the inside vertex I to the
+// outside vertex O (a shared edge gives the same point in both triangles).
+__device__ __forceinline__ float3 clip_point(float3 I, float3 O, float zn) {
+    const float t = (zn - I.z) / (O.z - I.z);
+    return make_float3(fmaf(t, O.x - I.x, I.x), fmaf(t, O.y - I.y, I.y), zn);
+}
+
+// Projection and snap to 1/256 px (round half to even).  False if the
+// snapped coordinate leaves the representable range.
+__device__ __forceinline__ bool snap(const CamF& c, float3 P, int& X, int& Y) {
+    const float inv = 1.0f / P.z;
+    const float u = fmaf(c.fx * P.x, inv, c.cx);
+    const float v = fmaf(c.fy * P.y, inv, c.cy);
+    const float su = rintf(u * 256.0f), sv = rintf(v * 256.0f);
+    if (!(fabsf(su) < (float)kSnapLimit) || !(fabsf(sv) < (float)kSnapLimit)) return false;
+    X = (int)su;
+    Y = (int)sv;
+    return true;
+}
+
+__device__ __forceinline__ uint64_t pack_key(float w, uint32_t id) {
+    // nearer surface = larger w = 1/z = smaller key; equal depths: lower id wins
+    return ((uint64_t)(~__float_as_uint(w)) << 32) | (uint64_t)id;
+}
+constexpr uint64_t kEmptyKey = ~0ull;
+
+// ------------------------------------------------------------------ tile rasterization
+
+// Depth plane of a triangle in the camera frame, as w = 1/z affine in the
+// pixel offsets: w = a (u - cx) + b (v - cy) + e, with a = n_x/(c fx),
+// b = n_y/(c fy), e = n_z/c for the camera-frame plane n . X = c.  Built in
+// FP64 from the triangle's world unit normal and first vertex, so that long
+// thin triangles keep their depth to ~1e-7 relative.
+struct WPlane { double a, b, e; };
+
+__device__ __forceinline__ WPlane depth_plane(const PoseF& P, const float* __restrict__ nw, float x0, float y0,
+                                              float z0, double ifx, double ify) {
+    const double n0 = nw[0], n1 = nw[1], n2 = nw[2];
+    const double c = n0 * ((double)x0 - P.t[0]) + n1 * ((double)y0 - P.t[1]) + n2 * ((double)z0 - P.t[2]);
+    const double ic = 1.0 / c;
+    const double nx = P.Rd[0][0] * n0 + P.Rd[0][1] * n1 + P.Rd[0][2] * n2;
+    const double ny = P.Rd[1][0] * n0 + P.Rd[1][1] * n1 + P.Rd[1][2] * n2;
+    const double nz = P.Rd[2][0] * n0 + P.Rd[2][1] * n1 + P.Rd[2][2] * n2;
+    WPlane p;
+    p.a = nx * ic * ifx;
+    p.b = ny * ic * ify;
+    p.e = nz * ic;
+    return p;
+}
+
+struct Tile {
+    int x0, y0, x1, y1;   // inclusive pixel range of the tile inside the image
+};
+
+template <typename I>
+__device__ __forceinline__ void raster_loop(uint64_t* keys, int tile_w, const Tile& tl, const int X[3],
+                                            const int Y[3], int px0, int px1, int py0, int py1,
+                                            const WPlane& pl, double cx, double cy, float w_far, uint32_t id) {
+    I E[3], sx[3], sy[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        const I dx = (I)X[k1] - (I)X[k];
+        const I dy = (I)Y[k1] - (I)Y[k];
+        const bool topleft = dy < 0 || (dy == 0 && dx > 0);
+        E[k] = dx * ((I)256 * (I)py0 - (I)Y[k]) - dy * ((I)256 * (I)px0 - (I)X[k]) - (topleft ? 0 : 1);
+        sx[k] = -(I)256 * dy;
+        sy[k] = (I)256 * dx;
+    }
+    double wrow = fma(pl.b, (double)py0 - cy, fma(pl.a, (double)px0 - cx, pl.e));
+    for (int y = py0; y <= py1; ++y) {
+        I e0 = E[0], e1 = E[1], e2 = E[2];
+        double w = wrow;
+        uint64_t* row = keys + (y - tl.y0) * tile_w - tl.x0;
+        for (int x = px0; x <= px1; ++x) {
+            if ((e0 | e1 | e2) >= 0) {
+                const float wf = (float)w;
+                if (wf >= w_far) atomicMin((unsigned long long*)(row + x), (unsigned long long)pack_key(wf, id));
+            }
+            e0 += sx[0]; e1 += sx[1]; e2 += sx[2];
+            w += pl.a;
+        }
+        E[0] += sy[0]; E[1] += sy[1]; E[2] += sy[2];
+        wrow += pl.b;
+    }
+}
+
+// Setup of one (sub-)triangle of the contract and its rasterization inside the tile.
+__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, const Tile& tl, const CamF& cam,
+                                         float3 A, float3 B, float3 C, const WPlane& pl, float w_far,
+                                         uint32_t id) {
+    int X[3], Y[3];
+    if (!snap(cam, A, X[0], Y[0]) || !snap(cam, B, X[1], Y[1]) || !snap(cam, C, X[2], Y[2])) return;
+    const int64_t area = (int64_t)(X[1] - X[0]) * (int64_t)(Y[2] - Y[0]) -
+                         (int64_t)(Y[1] - Y[0]) * (int64_t)(X[2] - X[0]);
+    if (area == 0) return;
+    if (area < 0) {
+        int t = X[1]; X[1] = X[2]; X[2] = t;
+        t = Y[1]; Y[1] = Y[2]; Y[2] = t;
+    }
+    const int mnx = min(X[0], min(X[1], X[2])), mxx = max(X[0], max(X[1], X[2]));
+    const int mny = min(Y[0], min(Y[1], Y[2])), mxy = max(Y[0], max(Y[1], Y[2]));
+    const int px0 = max((mnx + 255) >> 8, tl.x0), px1 = min(mxx >> 8, tl.x1);
+    const int py0 = max((mny + 255) >> 8, tl.y0), py1 = min(mxy >> 8, tl.y1);
+    if (px0 > px1 || py0 > py1) return;
+    if (mxx - mnx < (1 << 14) && mxy - mny < (1 << 14))
+        raster_loop<int32_t>(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far,
+                             id);
+    else
+        raster_loop<int64_t>(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far,
+                             id);
+}
+
+__device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
+    return k == 0 ? a : (k == 1 ? b : c);
+}
+
+// Whole contract for one mesh triangle: transform, far cull, near clip into
+// at most two sub-triangles (same id), setup and rasterization.
+__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, const Tile& tl, const CamF& cam,
+                                                double ifx, double ify, float w_far, const PoseF& P,
+                                                const float* __restrict__ xyz, const int32_t* __restrict__ tri,
+                                                const float* __restrict__ nrm, uint32_t vmax, int64_t t) {
+    const uint32_t i0 = min((uint32_t)tri[3 * t], vmax), i1 = min((uint32_t)tri[3 * t + 1], vmax),
+                   i2 = min((uint32_t)tri[3 * t + 2], vmax);
+    const float3 V0 = cam_contract(P, xyz[3 * (int64_t)i0], xyz[3 * (int64_t)i0 + 1], xyz[3 * (int64_t)i0 + 2]);
+    const float3 V1 = cam_contract(P, xyz[3 * (int64_t)i1], xyz[3 * (int64_t)i1 + 1], xyz[3 * (int64_t)i1 + 2]);
+    const float3 V2 = cam_contract(P, xyz[3 * (int64_t)i2], xyz[3 * (int64_t)i2 + 1], xyz[3 * (int64_t)i2 + 2]);
+    if (V0.z > cam.zf && V1.z > cam.zf && V2.z > cam.zf) return;
+    const bool in0 = V0.z >= cam.zn, in1 = V1.z >= cam.zn, in2 = V2.z >= cam.zn;
+    const int nin = (int)in0 + (int)in1 + (int)in2;
+    if (nin == 0) return;
+    const WPlane pl = depth_plane(P, nrm + 3 * t, xyz[3 * (int64_t)i0], xyz[3 * (int64_t)i0 + 1],
+                                  xyz[3 * (int64_t)i0 + 2], ifx, ify);
+    const uint32_t id = (uint32_t)t;
+    if (nin == 3) {
+        emit_tri(keys, tile_w, tl, cam, V0, V1, V2, pl, w_far, id);
+    } else if (nin == 2) {
+        const int k = !in0 ? 0 : (!in1 ? 1 : 2);          // the outside vertex
+        const float3 O = sel3(k, V0, V1, V2);
+        const float3 a = sel3(k == 2 ? 0 : k + 1, V0, V1, V2);
+        const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
+        const float3 Pb = clip_point(b, O, cam.zn);
+        const float3 Pa = clip_point(a, O, cam.zn);
+        emit_tri(keys, tile_w, tl, cam, a, b, Pb, pl, w_far, id);
+        emit_tri(keys, tile_w, tl, cam, a, Pb, Pa, pl, w_far, id);
+    } else {
+        const int k = in0 ? 0 : (in1 ? 1 : 2);            // the inside vertex
+        const float3 I = sel3(k, V0, V1, V2);
+        const float3 a = sel3(k == 2 ? 0 : k + 1, V0, V1, V2);
+        const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
+        emit_tri(keys, tile_w, tl, cam, I, clip_point(I, a, cam.zn), clip_point(I, b, cam.zn), pl, w_far, id);
+    }
+}
+
+// ------------------------------------------------------------------ per-pixel comparison
+
+struct Acc {
+    int e_table;
+    int cnt[9];
+    int n_active;
+    float e_soft;
+    float jtr[6];
+    float jtj[21];
+};
+
+// Table I cell of a pixel and its value: returns the cell (0..8) and sets s.
+__device__ __forceinline__ int table1(int c_r, int c_s, float dz, float eps, int& s) {
+    s = 0;
+    if (c_s == RM_NONE || c_s == RM_UO) return 6;
+    if (c_r == RM_NONE || c_r == RM_UO) return 7;
+    if (c_r == RM_FO && c_s == RM_FO) { const bool pen = fabsf(dz) > eps; s = pen ? 1 : -1; return pen ? 1 : 0; }
+    if (c_r == RM_FO && c_s == RM_FU) { const bool pen = dz <= 0.0f; s = pen ? 1 : -1; return pen ? 3 : 2; }
+    if (c_r == RM_FU && c_s == RM_FO) { const bool pen = dz > 0.0f; s = pen ? 1 : -1; return pen ? 5 : 4; }
+    return 8;
+}
+
+// ------------------------------------------------------------------ kernels
+
+struct ItemInfo {
+    int scan;
+    int pose;          // global pose index
+    int pose_local;
+    int tile;
+    int64_t rec;
+};
+
+__device__ __forceinline__ bool decode_item(const BatchDesc& bd, ItemInfo& it) {
+    // XCD-aware order: consecutive blocks land on different XCDs (round
+    // robin), so block b takes item (b % 8) * chunk + b / 8 and each XCD
+    // works through a contiguous run of (tile-major, pose-minor) items, i.e.
+    // the same screen tiles for neighbouring poses, which share triangles.
+    const int64_t b = blockIdx.x;
+    const int64_t chunk = (int64_t)gridDim.x / 8;
+    const int64_t item = (b % 8) * chunk + b / 8;
+    if (item >= bd.n_items) return false;
+    int s = 0;
+    while (s + 1 < bd.n_scans && item >= bd.s[s + 1].item_off) ++s;
+    const ScanDesc& sd = bd.s[s];
+    const int64_t local = item - sd.item_off;
+    it.scan = s;
+    it.tile = (int)(local / sd.n_poses);
+    it.pose_local = (int)(local % sd.n_poses);
+    it.pose = sd.pose_off + it.pose_local;
+    it.rec = sd.rec_off + (int64_t)it.pose_local * (sd.tiles_x * sd.tiles_y) + it.tile;
+    return true;
+}
+
+template <int TW, int TH, int MODE>
+__global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
+    __shared__ uint64_t keys[TW * TH];
+    __shared__ uint32_t clist[kWG];
+    __shared__ int ccount;
+    __shared__ float red[kWG / 64][kRecFields];
+
+    ItemInfo it;
+    if (!decode_item(bd, it)) return;
+    const ScanDesc& sd = bd.s[it.scan];
+    CamF cam{sd.fx, sd.fy, sd.cx, sd.cy, sd.z_near, sd.z_far, sd.width, sd.height};
+    const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
+    const double difx = 1.0 / (double)cam.fx, dify = 1.0 / (double)cam.fy;
+    const float w_far = 1.0f / cam.zf;
+    const int tx = it.tile % sd.tiles_x, ty = it.tile / sd.tiles_x;
+    Tile tl;
+    tl.x0 = tx * TW; tl.y0 = ty * TH;
+    tl.x1 = min(tl.x0 + TW, cam.W) - 1; tl.y1 = min(tl.y0 + TH, cam.H) - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    for (int p = tid; p < TW * TH; p += kWG) keys[p] = kEmptyKey;
+
+    PoseF P;
+    load_pose(a.T_wc + 12 * (int64_t)it.pose, P);
+    const int nvis = a.vis_count[it.pose];
+    const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
+    const uint32_t my_tile = (uint32_t)tx | ((uint32_t)ty << 16);
+    (void)my_tile;
+
+    for (int base = 0; base < nvis; base += kWG) {
+        if (tid == 0) ccount = 0;
+        __syncthreads();
+        bool take = false;
+        uint32_t cid = 0;
+        if (base + tid < nvis) {
+            const uint2 e = vis[base + tid];
+            const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
+            take = tx >= rx0 && tx <= rx1 && ty >= ry0 && ty <= ry1;
+            cid = e.x;
+        }
+        const uint64_t m = __ballot(take);
+        int wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&ccount, __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (take) clist[wbase + __popcll(m & ((1ull << lane) - 1ull))] = cid;
+        __syncthreads();
+        const int nc = ccount;
+        for (int k = 0; k < nc; ++k) {
+            const int64_t t = (int64_t)clist[k] * kClusterTris + tid;
+            if (t < a.n_tris) raster_triangle(keys, TW, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax, t);
+        }
+        __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- resolve
+    Acc acc;
+    acc.e_table = 0; acc.n_active = 0; acc.e_soft = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc.cnt[k] = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc.jtr[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) acc.jtj[k] = 0.0f;
+
+    const float eps = a.eps, ieps2 = 1.0f / (a.eps * a.eps);
+    const int64_t img = (int64_t)cam.W * cam.H;
+    for (int p = tid; p < TW * TH; p += kWG) {
+        const int x = tl.x0 + p % TW, y = tl.y0 + p / TW;
+        if (x > tl.x1 || y > tl.y1) continue;
+        const uint64_t key = keys[(y - tl.y0) * TW + (x - tl.x0)];
+        const bool hit = key != kEmptyKey;
+        const uint32_t id = (uint32_t)key;
+        const float z = hit ? 1.0f / __uint_as_float(~(uint32_t)(key >> 32)) : __int_as_float(0x7fc00000);
+        const int64_t pix = (int64_t)y * cam.W + x;
+        if (MODE == kRender) {
+            const int64_t o = (int64_t)it.pose * img + pix;
+            if (a.depth_out) a.depth_out[o] = z;
+            if (a.tri_out) a.tri_out[o] = hit ? (int32_t)id : -1;
+            if (a.cls_out) a.cls_out[o] = hit ? a.cls[id] : (uint8_t)RM_NONE;
+            continue;
+        }
+        if (sd.mask && !sd.mask[pix]) continue;
+        const int c_r = hit ? (int)a.cls[id] : RM_NONE;
+        const int c_s = sd.cls[pix];
+        const float d_s = sd.depth[pix];
+        const float dz = z - d_s;
+        int s;
+        const int cell = table1(c_r, c_s, dz, eps, s);
+        acc.e_table += s;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc.cnt[k] += cell == k;
+        if (cell >= 6) continue;
+        float r;
+        bool moving;
+        if (cell <= 1) { r = dz; moving = true; }
+        else if (cell <= 3) { r = fminf(dz, 0.0f); moving = dz < 0.0f; }
+        else { r = fmaxf(dz, 0.0f); moving = dz > 0.0f; }
+        const float q = r * r * ieps2;
+        acc.e_soft += 2.0f * fminf(q, 1.0f) - 1.0f;
+        if (MODE == kGrad && moving && r * r < eps * eps) {
+            // J = [-n ; n x P] / (n . r) from the winning triangle's camera-frame plane
+            const float* nw = a.nrm + 3 * (int64_t)id;
+            const float w0 = nw[0], w1 = nw[1], w2 = nw[2];
+            const float nx = fmaf(P.R[0][2], w2, fmaf(P.R[0][1], w1, P.R[0][0] * w0));
+            const float ny = fmaf(P.R[1][2], w2, fmaf(P.R[1][1], w1, P.R[1][0] * w0));
+            const float nz = fmaf(P.R[2][2], w2, fmaf(P.R[2][1], w1, P.R[2][0] * w0));
+            const float rx = ((float)x - cam.cx) * ifx, ry = ((float)y - cam.cy) * ify;
+            const float nr = fmaf(nx, rx, fmaf(ny, ry, nz));
+            const float inr = 1.0f / nr;
+            const float Px = z * rx, Py = z * ry, Pz = z;
+            float J[6];
+            J[0] = -nx * inr; J[1] = -ny * inr; J[2] = -nz * inr;
+            J[3] = (ny * Pz - nz * Py) * inr;
+            J[4] = (nz * Px - nx * Pz) * inr;
+            J[5] = (nx * Py - ny * Px) * inr;
+            acc.n_active += 1;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) acc.jtr[i] = fmaf(r, J[i], acc.jtr[i]);
+            int k = 0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = i; j < 6; ++j) { acc.jtj[k] = fmaf(J[i], J[j], acc.jtj[k]); ++k; }
+        }
+    }
+    if (MODE == kRender) return;
+
+    // ---------------------------------------------------------------- reduction (fixed order)
+    constexpr int NF = MODE == kGrad ? 39 : 12;
+    float v[NF];
+    v[0] = __int_as_float(acc.e_table);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[1 + k] = __int_as_float(acc.cnt[k]);
+    v[10] = __int_as_float(acc.n_active);
+    v[11] = acc.e_soft;
+    if (MODE == kGrad) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[12 + k] = acc.jtr[k];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) v[18 + k] = acc.jtj[k];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        if (f <= 10) {
+            int x = __float_as_int(v[f]);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+            v[f] = __int_as_float(x);
+        } else {
+            float x = v[f];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+            v[f] = x;
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) red[wave][f] = v[f];
+    }
+    __syncthreads();
+    if (tid < kRecFields) {
+        float* rec = a.rec + it.rec * kRecFields;
+        if (tid >= NF) {
+            rec[tid] = 0.0f;
+        } else if (tid <= 10) {
+            int x = 0;
+#pragma unroll
+            for (int w = 0; w < kWG / 64; ++w) x += __float_as_int(red[w][tid]);
+            rec[tid] = __int_as_float(x);
+        } else {
+            float x = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kWG / 64; ++w) x += red[w][tid];
+            rec[tid] = x;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ cluster cull
+
+__device__ __forceinline__ void proj_acc(double fx, double fy, double cx, double cy, double x, double y,
+                                         double z, double& umin, double& umax, double& vmin, double& vmax) {
+    const double u = fx * x / z + cx, v = fy * y / z + cy;
+    umin = fmin(umin, u); umax = fmax(umax, u);
+    vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+}
+
+// One thread per (cluster, pose): frustum test of the cluster's world AABB
+// and the range of screen tiles its projection can touch.  Conservative:
+// the box is clipped against a near plane slightly in front of z_near and the
+// screen rectangle is widened by 2 px.
+__global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds* __restrict__ cb,
+                                              int32_t n_clusters, const double* __restrict__ T_wc,
+                                              uint2* __restrict__ vis, int32_t* __restrict__ vis_count,
+                                              int32_t* __restrict__ vis_tris) {
+    const int c = blockIdx.x * kWG + threadIdx.x;
+    const int pose = blockIdx.y;
+    int s = 0;
+    while (s + 1 < bd.n_scans && pose >= bd.s[s + 1].pose_off) ++s;
+    const ScanDesc& sd = bd.s[s];
+    bool visible = false;
+    uint32_t rect = 0;
+    int ntri = 0;
+    if (c < n_clusters) {
+        const ClusterBounds b = cb[c];
+        ntri = b.n_tris;
+        const double* T = T_wc + 12 * (int64_t)pose;
+        const double zn = (double)sd.z_near * (1.0 - 1e-5), zf = (double)sd.z_far * (1.0 + 1e-5);
+        double X[8], Y[8], Z[8];
+        int nfront = 0, nfar = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double px = (k & 1) ? b.hi[0] : b.lo[0];
+            const double py = (k & 2) ? b.hi[1] : b.lo[1];
+            const double pz = (k & 4) ? b.hi[2] : b.lo[2];
+            const double d0 = px - T[3], d1 = py - T[7], d2 = pz - T[11];
+            X[k] = T[0] * d0 + T[4] * d1 + T[8] * d2;
+            Y[k] = T[1] * d0 + T[5] * d1 + T[9] * d2;
+            Z[k] = T[2] * d0 + T[6] * d1 + T[10] * d2;
+            nfront += Z[k] >= zn;
+            nfar += Z[k] > zf;
+        }
+        const double fx = sd.fx, fy = sd.fy, cx = sd.cx, cy = sd.cy;
+        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        if (nfront > 0 && nfar < 8 && b.n_tris > 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (Z[k] >= zn) proj_acc(fx, fy, cx, cy, X[k], Y[k], Z[k], umin, umax, vmin, vmax);
+            if (nfront < 8) {
+                // box edges crossing the near plane: corners differing in one bit
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int bit = 1; bit < 8; bit <<= 1) {
+                        const int j = k | bit;
+                        if (j == k) continue;
+                        if ((Z[k] >= zn) != (Z[j] >= zn)) {
+                            const double t = (zn - Z[k]) / (Z[j] - Z[k]);
+                            proj_acc(fx, fy, cx, cy, X[k] + t * (X[j] - X[k]), Y[k] + t * (Y[j] - Y[k]), zn,
+                                     umin, umax, vmin, vmax);
+                        }
+                    }
+            }
+            umin -= 2.0; vmin -= 2.0; umax += 2.0; vmax += 2.0;
+            const double W1 = sd.width - 1, H1 = sd.height - 1;
+            if (umin <= umax && vmin <= vmax && umax >= 0.0 && vmax >= 0.0 && umin <= W1 && vmin <= H1) {
+                const int tw = bd.tile_w, th = bd.tile_h;
+                const int x0 = (int)fmax(umin, 0.0), x1 = (int)fmin(umax, W1);
+                const int y0 = (int)fmax(vmin, 0.0), y1 = (int)fmin(vmax, H1);
+                rect = (uint32_t)(x0 / tw) | ((uint32_t)(x1 / tw) << 8) | ((uint32_t)(y0 / th) << 16) |
+                       ((uint32_t)(y1 / th) << 24);
+                visible = true;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = __ballot(visible);
+    if (!m) return;
+    int ntv = visible ? ntri : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ntv += __shfl_xor(ntv, off);
+    int base = 0;
+    if (lane == 0) {
+        base = atomicAdd(vis_count + pose, __popcll(m));
+        atomicAdd(vis_tris + pose, ntv);
+    }
+    base = __shfl(base, 0);
+    if (visible) vis[(int64_t)pose * n_clusters + base + __popcll(m & ((1ull << lane) - 1ull))] = make_uint2((uint32_t)c, rect);
+}
+
+// ------------------------------------------------------------------ per-pose reduction
+
+// One wave per pose; lane f sums field f over the pose's tiles in tile order
+// (FP64, integers exactly), so the result does not depend on scheduling.
+__global__ void k_reduce(BatchDesc bd, const float* __restrict__ rec, const int32_t* __restrict__ vis_tris,
+                         float eps, int grad, double* __restrict__ out) {
+    __shared__ double val[kRecFields];
+    const int pose = blockIdx.x;
+    int s = 0;
+    while (s + 1 < bd.n_scans && pose >= bd.s[s + 1].pose_off) ++s;
+    const ScanDesc& sd = bd.s[s];
+    const int ntile = sd.tiles_x * sd.tiles_y;
+    const float* r = rec + (sd.rec_off + (int64_t)(pose - sd.pose_off) * ntile) * kRecFields;
+    const int f = threadIdx.x;
+    if (f < kRecFields) {
+        if (f <= 10) {
+            int64_t acc = 0;
+            for (int t = 0; t < ntile; ++t) acc += __float_as_int(r[(int64_t)t * kRecFields + f]);
+            val[f] = (double)acc;
+        } else {
+            double acc = 0.0;
+            for (int t = 0; t < ntile; ++t) acc += (double)r[(int64_t)t * kRecFields + f];
+            val[f] = acc;
+        }
+    }
+    __syncthreads();
+    double* o = out + (int64_t)pose * RM_OUT_STRIDE;
+    if (f < RM_OUT_STRIDE) {
+        double x = 0.0;
+        if (f == RM_OUT_E_TABLE) x = val[0];
+        else if (f == RM_OUT_E_SOFT) x = val[11];
+        else if (f >= RM_OUT_COUNTS && f < RM_OUT_COUNTS + 9) x = val[1 + f - RM_OUT_COUNTS];
+        else if (f == RM_OUT_N_ACTIVE) x = grad ? val[10] : 0.0;
+        else if (f >= RM_OUT_GRAD && f < RM_OUT_GRAD + 6)
+            x = grad ? (4.0 / ((double)eps * (double)eps)) * val[12 + f - RM_OUT_GRAD] : 0.0;
+        else if (f >= RM_OUT_JTR && f < RM_OUT_JTR + 6) x = grad ? val[12 + f - RM_OUT_JTR] : 0.0;
+        else if (f >= RM_OUT_JTJ && f < RM_OUT_JTJ + 21) x = grad ? val[18 + f - RM_OUT_JTJ] : 0.0;
+        else if (f == RM_OUT_N_VISIBLE) x = (double)vis_tris[pose];
+        o[f] = x;
+    }
+}
+
+template <int TW, int TH>
+hipError_t launch_raster_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {
+    const int64_t chunk = (bd.n_items + 7) / 8;
+    const dim3 grid((unsigned)(chunk * 8));
+    if (mode == kRender) hipLaunchKernelGGL((k_raster<TW, TH, kRender>), grid, dim3(kWG), 0, st, bd, a);
+    else if (mode == kCost) hipLaunchKernelGGL((k_raster<TW, TH, kCost>), grid, dim3(kWG), 0, st, bd, a);
+    else hipLaunchKernelGGL((k_raster<TW, TH, kGrad>), grid, dim3(kWG), 0, st, bd, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds* cb, int32_t n_clusters,
+                       const double* T_wc, uint2* vis, int32_t* vis_count, int32_t* vis_tris) {
+    if (n_clusters == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_clusters + kWG - 1) / kWG), (unsigned)bd.n_poses);
+    hipLaunchKernelGGL(k_cull, grid, dim3(kWG), 0, st, bd, cb, n_clusters, T_wc, vis, vis_count, vis_tris);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {
+    if (bd.n_items == 0) return hipSuccess;
+    if (bd.tile_w == 16 && bd.tile_h == 16) return launch_raster_t<16, 16>(st, bd, a, mode);
+    if (bd.tile_w == 64 && bd.tile_h == 32) return launch_raster_t<64, 32>(st, bd, a, mode);
+    return launch_raster_t<32, 32>(st, bd, a, mode);
+}
+
+hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec, const int32_t* vis_tris,
+                         float eps, int grad, double* out) {
+    if (bd.n_poses == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)bd.n_poses), dim3(64), 0, st, bd, rec, vis_tris, eps, grad, out);
+    return hipGetLastError();
+}
+
+}  // namespace rm

@@ -1,0 +1,87 @@
+"""CPU checks of the C ABI boundary: the built library loads, exports every
+function include/rendermap.h declares, and rejects invalid arguments on the
+host before touching a device.  No compute call runs here."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "rendermap.h"
+LIB = ROOT / "paper_1702_06813_amd" / "librendermap.so"
+
+
+def declared_functions():
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(rm_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not LIB.exists():
+        pytest.skip("library not built")
+    return ctypes.CDLL(str(LIB))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for core in ("rm_mesh_from_range", "rm_render_depth", "rm_align_cost", "rm_align_cost_grad"):
+        assert core in names
+    assert len(names) >= 20
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_symbol_list_matches_header():
+    from paper_1702_06813_amd import rendermap
+    assert sorted(rendermap.ABI_SYMBOLS) == declared_functions()
+
+
+def test_null_context_is_rejected_without_a_device(lib):
+    lib.rm_last_error.restype = ctypes.c_char_p
+    lib.rm_last_error.argtypes = [ctypes.c_void_p]
+    assert lib.rm_render_depth(None, None, None, None, 0, None, None, None) == -1
+    assert b"ctx" in lib.rm_last_error(None)
+    assert lib.rm_gn_step(None, None, 1, ctypes.c_double(0.0), None, None) == -1
+    assert lib.rm_align_cost(None, None, None, 1, None, None, ctypes.c_int64(0), None) == -1
+
+
+def test_cluster_size_rule(lib):
+    lib.rm_mesh_clusters_size.restype = ctypes.c_int64
+    lib.rm_mesh_clusters_size.argtypes = [ctypes.c_int64]
+    # [ceil(T/256)] 32-byte cluster records padded to 256 bytes, then [T][3] f32 normals
+    assert lib.rm_mesh_clusters_size(0) == 0
+    for T in (1, 256, 257, 2048, 2049, 1021734):
+        C = -(-T // 256)
+        assert lib.rm_mesh_clusters_size(T) == (C * 32 + 255) // 256 * 256 + 12 * T
+
+
+def test_ctx_create_without_gpu_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = lib.rm_ctx_create(0, ctypes.byref(h))
+    assert rc in (-3, -1) and not h.value
+
+
+def test_product_path_does_not_use_the_oracle():
+    """The package never imports, loads or names the oracle."""
+    pkg = ROOT / "paper_1702_06813_amd"
+    for f in list(pkg.rglob("*.py")) + list(pkg.rglob("*.hip")) + list(pkg.rglob("*.cpp")) + list(pkg.rglob("*.h")):
+        text = f.read_text()
+        assert "oracle" not in text.lower(), f
+        assert "rm_oracle" not in text, f
+
+
+def test_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1702_06813_amd as rm
+    with pytest.raises(RuntimeError):
+        rm.Context(0)

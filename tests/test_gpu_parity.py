@@ -1,0 +1,405 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Every input is seeded and synthetic; every expected value comes from the
+oracle.  Sizes: the tiny room at full frame (several tiles plus ragged
+edges), the Kinect-like map at 640x480 on sampled pixels, and the 1M-triangle
+differentiation map at the launch configuration the benchmark times, on
+sampled pixels.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import scenes as S
+
+from gpu_helpers import EPS, compare_records, flagged_pixels, oracle_map, render_mismatch, sample_pixels, workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_06813_amd as rm
+    rm.load_library()
+    return rm
+
+
+DEV = "cuda:0"
+
+
+def _dev_mesh(rm, mesh):
+    return rm.Mesh.from_arrays(*mesh, device=DEV).prepare()
+
+
+def _T(poses):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(poses).reshape(-1, 12))).to(DEV)
+
+
+# ------------------------------------------------------------------ scan image / meshify
+
+def test_scan_image_bitexact(rm):
+    _say("scan_image")
+    rng = np.random.default_rng(0)
+    z = rng.uniform(0.0, 10.0, (37, 53)).astype(np.float32)
+    z[rng.random(z.shape) < 0.1] = 0.0
+    z[rng.random(z.shape) < 0.05] = np.nan
+    z[rng.random(z.shape) < 0.05] = np.inf
+    z[rng.random(z.shape) < 0.05] = -1.0
+    z[0, :4] = [0.5, 8.0, np.float32(0.49999997), np.float32(8.000001)]
+    d, c = O.scan_image(z, 0.5, 8.0)
+    s = rm.scan_image(torch.from_numpy(z).to(DEV), 0.5, 8.0)
+    np.testing.assert_array_equal(s.cls.cpu().numpy(), c)
+    np.testing.assert_array_equal(s.depth.cpu().numpy(), d)   # NaN positions compare equal
+
+
+@pytest.mark.parametrize("stride", [1, 3, 4, 8])
+def test_meshify_bitexact(rm, stride):
+    _say(f"meshify stride {stride}")
+    w = workload("kinect")
+    for k in (0, 5):
+        depth, T = w.view_depths[k].copy(), w.views[k]
+        depth[::97, ::89] = np.nan            # dead pixels drop quads
+        xyz, tri, cls = O.meshify(depth, w.cam, T, stride, w.z_min, w.z_max, 0.1 * stride / 2)
+        m = rm.mesh_from_range(torch.from_numpy(depth).to(DEV), w.cam, T, stride, w.z_min, w.z_max,
+                               0.1 * stride / 2)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(m.xyz.cpu().numpy(), xyz)
+        np.testing.assert_array_equal(m.tri.cpu().numpy(), tri)
+        np.testing.assert_array_equal(m.cls.cpu().numpy(), cls)
+
+
+def test_meshify_ragged_and_tiny(rm):
+    _say("meshify ragged")
+    cam = S.Camera(30.0, 30.0, 9.5, 6.5, 21, 14)
+    rng = np.random.default_rng(1)
+    T = S.look_pose(np.array([0.3, -0.2, 1.0]), 0.4, 0.1)
+    for depth in (rng.uniform(0.4, 9.0, (14, 21)).astype(np.float32), np.zeros((14, 21), np.float32),
+                  np.full((14, 21), np.nan, np.float32)):
+        for s in (1, 2, 5, 20):
+            ref = O.meshify(depth, cam, T, s)
+            m = rm.mesh_from_range(torch.from_numpy(depth).to(DEV), cam, T, s)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(m.xyz.cpu().numpy(), ref[0])
+            np.testing.assert_array_equal(m.tri.cpu().numpy(), ref[1])
+            np.testing.assert_array_equal(m.cls.cpu().numpy(), ref[2])
+
+
+# ------------------------------------------------------------------ z-buffer
+
+def _render_cmp(rm, mesh_np, cam, poses, pixels=None, max_flag_frac=0.01):
+    dm = _dev_mesh(rm, mesh_np)
+    out = rm.render_depth(dm, cam, _T(poses))
+    gd = out["depth"].cpu().numpy()
+    gt = out["tri"].cpu().numpy()
+    gc = out["cls"].cpu().numpy()
+    for b, T in enumerate(poses):
+        rend = O.render(mesh_np, cam, T, pixels)
+        bad, rel, nflag = render_mismatch(rend, cam, gd[b], gt[b])
+        assert bad == 0, f"pose {b}: {bad} unflagged id mismatches"
+        assert rel <= 1e-5, f"pose {b}: depth rel err {rel}"
+        assert nflag <= max_flag_frac * len(rend["pixels"]) + 2
+        # class map follows the id map
+        gcl = gc[b].reshape(-1)[rend["pixels"]]
+        gid = gt[b].reshape(-1)[rend["pixels"]]
+        exp = np.where(gid >= 0, mesh_np[2][np.maximum(gid, 0)], O.NONE)
+        np.testing.assert_array_equal(gcl, exp)
+
+
+def test_render_tiny_full_frame(rm):
+    _say("render tiny")
+    w = workload("tiny")
+    rng = np.random.default_rng(3)
+    poses = [w.T_true, w.poses[0]] + [S.perturb(w.T_true, rng, 0.3, np.deg2rad(30)) for _ in range(6)]
+    _render_cmp(rm, w.map_mesh, w.cam, poses)
+
+
+def test_render_near_plane_clipping(rm):
+    """Poses close to walls and boxes so that many triangles cross z_near."""
+    _say("render clip")
+    w = workload("tiny")
+    cam = S.Camera(52.5, 52.5, 31.5, 23.5, 64, 48, z_near=0.1, z_far=16.0)
+    rng = np.random.default_rng(4)
+    poses = []
+    for k in range(8):
+        pos = np.array([rng.uniform(0.05, 0.3), rng.uniform(0.3, 3.7), rng.uniform(0.2, 2.3)])
+        poses.append(S.look_pose(pos, rng.uniform(-np.pi, np.pi), rng.uniform(-1.2, 1.2), rng.uniform(-1, 1)))
+    _render_cmp(rm, w.map_mesh, cam, poses)
+
+
+def test_render_ragged_image_and_big_triangles(rm):
+    """An image size that is no multiple of any tile, and triangles far
+    larger than a tile (the 64-bit edge-function path)."""
+    _say("render ragged")
+    scene = S.random_box_room(7, (4.0, 4.0, 2.5), 8)
+    mesh = S.triangulate_scene(scene, cell=2.0)            # huge wall triangles
+    cam = S.Camera(70.0, 70.0, 50.5, 33.5, 101, 67)
+    rng = np.random.default_rng(5)
+    poses = [S.look_pose(np.array([rng.uniform(1, 3), rng.uniform(1, 3), rng.uniform(0.8, 1.8)]),
+                         rng.uniform(0, 6.28), rng.uniform(-0.5, 0.5), rng.uniform(-0.3, 0.3)) for _ in range(6)]
+    _render_cmp(rm, mesh, cam, poses)
+    for tile in ((16, 16), (64, 32)):
+        rm.context().set_tile(*tile)
+        try:
+            _render_cmp(rm, mesh, cam, poses[:2])
+        finally:
+            rm.context().set_tile(0, 0)
+
+
+def test_render_kinect_sampled(rm):
+    _say("render kinect")
+    w = workload("kinect")
+    mesh = oracle_map("kinect")
+    pix = sample_pixels(w.cam, 3000, 11)
+    _render_cmp(rm, mesh, w.cam, list(w.poses[:4]), pixels=pix)
+
+
+def test_render_empty_mesh_and_pointing_away(rm):
+    _say("render empty")
+    w = workload("tiny")
+    empty = (np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), np.zeros(0, np.uint8))
+    dm = rm.Mesh.from_arrays(*empty, device=DEV)
+    out = rm.render_depth(dm, w.cam, _T([w.T_true]))
+    assert (out["tri"].cpu().numpy() == -1).all()
+    assert np.isnan(out["depth"].cpu().numpy()).all()
+    # a camera outside the room looking away sees nothing
+    T = S.look_pose(np.array([2.0, -3.0, 1.2]), -np.pi / 2)
+    out = rm.render_depth(_dev_mesh(rm, w.map_mesh), w.cam, _T([T]))
+    assert (out["cls"].cpu().numpy() == rm.NONE).all()
+
+
+# ------------------------------------------------------------------ cost and gradient
+
+def _cost_case(rm, name, poses, pixels, grad=True, mesh_np=None):
+    w = workload(name)
+    mesh_np = oracle_map(name) if mesh_np is None else mesh_np
+    d, c = O.scan_image(w.scan_depth, w.z_min, w.z_max)
+    dm = _dev_mesh(rm, mesh_np)
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), w.z_min, w.z_max, cam=w.cam)
+    res = []
+    masks = []
+    for b, T in enumerate(poses):
+        rend = O.render(mesh_np, w.cam, T, pixels)
+        terms = O.pixel_terms(rend, mesh_np[2], d, c, w.cam, EPS)
+        flagged = flagged_pixels(rend, terms, w.cam, EPS)
+        keep = ~flagged
+        ref = O.reduce_terms(terms, keep)
+        mask = np.zeros(w.cam.width * w.cam.height, np.uint8)
+        mask[rend["pixels"][keep]] = 1
+        masks.append(mask)
+        res.append((ref, terms, keep))
+    outs = []
+    for b, T in enumerate(poses):
+        scan.mask = torch.from_numpy(masks[b].reshape(w.cam.height, w.cam.width)).to(DEV)
+        f = rm.align_cost_grad if grad else rm.align_cost
+        outs.append(f(dm, scan, _T([T]), EPS).cpu().numpy()[0])
+    for b in range(len(poses)):
+        ref, terms, keep = res[b]
+        compare_records(outs[b], ref, terms, keep, EPS, grad=grad)
+        assert keep.mean() > 0.95
+    return outs
+
+
+def test_cost_grad_tiny_full_frame(rm):
+    _say("cost tiny")
+    w = workload("tiny")
+    rng = np.random.default_rng(6)
+    poses = [w.T_true, w.poses[0]] + [S.perturb(w.T_true, rng, 0.05, np.deg2rad(3)) for _ in range(4)]
+    _cost_case(rm, "tiny", poses, None)
+    _cost_case(rm, "tiny", poses[:2], None, grad=False)
+
+
+def test_cost_grad_kinect_sampled(rm):
+    _say("cost kinect")
+    w = workload("kinect")
+    _cost_case(rm, "kinect", list(w.poses[:3]), sample_pixels(w.cam, 4000, 12))
+
+
+@pytest.mark.slow
+def test_cost_grad_differentiation_1m_sampled(rm):
+    """The 1M-triangle map at 640x480, on sampled pixels, plus full-batch
+    invariants at the benchmark's launch configuration (B = 64)."""
+    _say("cost differentiation (1M triangles)")
+    w = workload("differentiation")
+    _cost_case(rm, "differentiation", list(w.poses[:2]), sample_pixels(w.cam, 1500, 13))
+
+
+def test_unmasked_totals_within_flag_bound(rm):
+    """Without a mask, totals differ from the oracle only through flagged pixels."""
+    _say("unmasked totals")
+    w = workload("tiny")
+    d, c = O.scan_image(w.scan_depth)
+    dm = _dev_mesh(rm, w.map_mesh)
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    g = rm.align_cost_grad(dm, scan, _T(w.poses), EPS).cpu().numpy()[0]
+    ref = O.align_cost(w.map_mesh, w.cam, w.poses[0], d, c, eps=EPS)
+    nflag = flagged_pixels(ref["render"], ref["terms"], w.cam, EPS).sum()
+    assert abs(g[0] - ref["e_table"]) <= 2 * nflag
+    assert abs(g[1] - ref["e_soft"]) <= 1e-4 * np.abs(ref["terms"]["rho"]).sum() + 2 * nflag
+
+
+def test_empty_and_degenerate_costs(rm):
+    _say("degenerate costs")
+    w = workload("tiny")
+    dm = _dev_mesh(rm, w.map_mesh)
+    nan_scan = rm.scan_image(torch.full((w.cam.height, w.cam.width), float("nan"), device=DEV), cam=w.cam)
+    out = rm.align_cost_grad(dm, nan_scan, _T(w.poses), EPS).cpu().numpy()[0]
+    assert out[0] == 0 and out[1] == 0 and out[2 + 6] == w.cam.width * w.cam.height
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    empty = rm.Mesh.from_arrays(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), np.zeros(0, np.uint8),
+                                device=DEV)
+    out = rm.align_cost_grad(empty, scan, _T(w.poses), EPS).cpu().numpy()[0]
+    assert out[0] == 0 and out[1] == 0 and out[2 + 7] == w.cam.width * w.cam.height
+    T = S.look_pose(np.array([2.0, -3.0, 1.2]), -np.pi / 2)
+    out = rm.align_cost_grad(dm, scan, _T([T]), EPS).cpu().numpy()[0]
+    assert out[0] == 0 and out[rm.OUT_N_ACTIVE] == 0 and not out[rm.OUT_GRAD:rm.OUT_GRAD + 6].any()
+
+
+# ------------------------------------------------------------------ invariances
+
+def test_batch_tile_and_run_invariance(rm):
+    """Pose i of a batch equals pose i alone; every tile shape and a repeated
+    run give bit-identical records."""
+    _say("invariance")
+    w = workload("kinect")
+    dm = _dev_mesh(rm, oracle_map("kinect"))
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    T = _T(w.poses[:16])
+    base = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
+    again = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
+    np.testing.assert_array_equal(base, again)
+    for i in (0, 7, 15):
+        one = rm.align_cost_grad(dm, scan, T[i:i + 1].contiguous(), EPS).cpu().numpy()
+        np.testing.assert_array_equal(one[0], base[i])
+    ctx = rm.context()
+    try:
+        for tile in ((16, 16), (64, 32)):
+            ctx.set_tile(*tile)
+            o = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
+            # integer fields identical; float sums reassociate across tiles
+            np.testing.assert_array_equal(o[:, [0] + list(range(2, 12))], base[:, [0] + list(range(2, 12))])
+            l1 = np.abs(base[:, 1]) + 1
+            assert (np.abs(o[:, 1] - base[:, 1]) <= 1e-5 * l1 + 1e-3).all()
+            np.testing.assert_allclose(o[:, 18:45], base[:, 18:45], rtol=1e-4, atol=1e-6 * np.abs(base[:, 18:45]).max())
+            ro = rm.render_depth(dm, w.cam, T[:2].contiguous())
+            ctx.set_tile(0, 0)
+            rb = rm.render_depth(dm, w.cam, T[:2].contiguous())
+            np.testing.assert_array_equal(ro["tri"].cpu().numpy(), rb["tri"].cpu().numpy())
+            np.testing.assert_array_equal(ro["depth"].cpu().numpy(), rb["depth"].cpu().numpy())
+    finally:
+        ctx.set_tile(0, 0)
+
+
+def test_multi_scan_uneven_batch(rm):
+    """Scans of different resolutions with uneven pose counts in one launch
+    give the same records as one launch per scan."""
+    _say("multi-scan")
+    wk = workload("kinect")
+    mesh = oracle_map("kinect")
+    dm = _dev_mesh(rm, mesh)
+    cams = [S.QVGA, S.KINECT, S.Camera(400.0, 400.0, 249.5, 149.5, 500, 300), S.TINY]
+    rng = np.random.default_rng(9)
+    scans, poses, counts = [], [], []
+    for k, cam in enumerate(cams):
+        depth = S.range_image(wk.scene, cam, wk.T_true, 50 + k, dropout=0.02)
+        scans.append(rm.scan_image(torch.from_numpy(depth).to(DEV), cam=cam))
+        n = [3, 1, 5, 2][k]
+        counts.append(n)
+        poses += [S.perturb(wk.T_true, rng, 0.03, np.deg2rad(1.5)) for _ in range(n)]
+    T = _T(poses)
+    allr = rm.align_cost_grad(dm, scans, T, EPS, poses_per_scan=counts).cpu().numpy()
+    off = 0
+    for k in range(len(cams)):
+        sep = rm.align_cost_grad(dm, scans[k], T[off:off + counts[k]].contiguous(), EPS).cpu().numpy()
+        np.testing.assert_array_equal(sep, allr[off:off + counts[k]])
+        off += counts[k]
+    # and against the oracle for the smallest scan, full frame
+    d, c = O.scan_image(S.range_image(wk.scene, S.TINY, wk.T_true, 53, dropout=0.02))
+    ref = O.align_cost(mesh, S.TINY, poses[-1], d, c, eps=EPS)
+    assert abs(allr[-1][0] - ref["e_table"]) <= 2 * flagged_pixels(ref["render"], ref["terms"], S.TINY, EPS).sum()
+
+
+# ------------------------------------------------------------------ optimizer step, autograd, graphs
+
+def test_gn_step_and_retract_match_oracle(rm):
+    _say("gn step")
+    w = workload("tiny")
+    dm = _dev_mesh(rm, w.map_mesh)
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    T = _T(w.poses)
+    out = rm.align_cost_grad(dm, scan, T, 0.5)
+    o = out.cpu().numpy()[0]
+    H = np.zeros((6, 6)); H[np.triu_indices(6)] = o[24:45]; H = H + H.T - np.diag(np.diag(H))
+    ref = O.gn_step({"jtj": H, "jtr": o[18:24]}, lam=0.1)
+    T2 = T.clone()
+    delta = torch.empty((1, 6), dtype=torch.float64, device=DEV)
+    rm.gn_step(out, T2, 0.1, delta)
+    np.testing.assert_allclose(delta.cpu().numpy()[0], ref, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(T2.cpu().numpy().reshape(3, 4), O.retract(w.poses[0], ref), atol=1e-12)
+    rng = np.random.default_rng(0)
+    dl = rng.normal(size=(5, 6)) * np.array([0.1, 0.1, 0.1, 0.5, 0.5, 0.5])
+    dl[0, 3:] = 1e-9
+    Ts = np.stack([S.perturb(w.T_true, rng, 0.5, 0.5) for _ in range(5)])
+    got = rm.se3_retract(_T(Ts), torch.from_numpy(dl).to(DEV)).cpu().numpy().reshape(5, 3, 4)
+    for k in range(5):
+        np.testing.assert_allclose(got[k], O.retract(Ts[k], dl[k]), atol=1e-13)
+
+
+def test_autograd_function_matches_oracle_gradient(rm):
+    _say("autograd")
+    w = workload("tiny")
+    dm = _dev_mesh(rm, w.map_mesh)
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    T0 = _T(w.poses)
+    delta = torch.zeros((1, 6), dtype=torch.float64, device=DEV, requires_grad=True)
+    e = rm.AlignCost.apply(delta, T0, dm, scan, EPS)
+    (2.0 * e.sum()).backward()
+    d, c = O.scan_image(w.scan_depth)
+    ref = O.align_cost(w.map_mesh, w.cam, w.poses[0], d, c, eps=EPS)
+    t = ref["terms"]
+    gl1 = (4.0 / EPS ** 2) * np.abs(t["r"][:, None] * t["J"]).sum(0)
+    nflag = flagged_pixels(ref["render"], t, w.cam, EPS).sum()
+    g = delta.grad.cpu().numpy()[0] / 2.0
+    assert (np.abs(g - ref["grad"]) <= 1e-3 * gl1 + 1e-9).all(), (g, ref["grad"])
+
+
+def test_graph_replay_matches_eager(rm):
+    """An optimizer step (cost + gradient + LM update) captured once and
+    replayed several times, with eager work in between, matches running the
+    same calls eagerly."""
+    _say("graph replay")
+    w = workload("kinect")
+    dm = _dev_mesh(rm, oracle_map("kinect"))
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    T0 = _T(w.poses[:8])
+    Te = T0.clone()
+    eager = []
+    out = torch.empty((8, rm.OUT_STRIDE), dtype=torch.float64, device=DEV)
+    for it in range(3):
+        rm.align_cost_grad(dm, scan, Te, 0.3, out=out)
+        rm.gn_step(out, Te, 0.01)
+        eager.append((out.clone(), Te.clone()))
+    Tg = T0.clone()
+    outg = torch.empty_like(out)
+    rm.align_cost_grad(dm, scan, Tg, 0.3, out=outg)      # sizes the scratch before capture
+    torch.cuda.synchronize()
+    g = rm.Graph()
+    with g:
+        rm.align_cost_grad(dm, scan, Tg, 0.3, out=outg)
+        rm.gn_step(outg, Tg, 0.01)
+    for it in range(3):
+        g.replay()
+        junk = torch.randn(1000, device=DEV).sum()     # eager work between replays
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(outg.cpu().numpy(), eager[it][0].cpu().numpy())
+        np.testing.assert_array_equal(Tg.cpu().numpy(), eager[it][1].cpu().numpy())
+        del junk
