@@ -31,6 +31,13 @@ struct rm_ctx {
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
     size_t prof_used = 0;
+    // tile-bin capacity, adapted from the largest bin of earlier calls
+    int32_t bin_cap = 1024;
+    hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bin
+    bool bin_pending = false;
+    // once a graph has been captured, scratch that it may reference is never freed early
+    bool captured = false;
+    std::vector<void*> retired;
 };
 
 namespace {
@@ -89,7 +96,10 @@ int ensure_scratch(rm_ctx* ctx, size_t bytes) {
         return fail(ctx, RM_ERR_CAPACITY, "scratch must grow to %zu bytes during stream capture; "
                                           "run the call once before capturing", bytes);
     RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->scratch) RM_HIP(ctx, hipFree(ctx->scratch));
+    if (ctx->scratch) {
+        if (ctx->captured) ctx->retired.push_back(ctx->scratch);
+        else RM_HIP(ctx, hipFree(ctx->scratch));
+    }
     ctx->scratch = nullptr;
     ctx->scratch_size = 0;
     const size_t sz = std::max(bytes + bytes / 4, (size_t)1 << 20);
@@ -158,22 +168,45 @@ int64_t total_records(const BatchDesc& bd) {
     return r;
 }
 
-// One scoring pass: cull, rasterize (+ fused comparison), reduce.
+constexpr int64_t kMaxBinBytes = (int64_t)4 << 30;    // largest tile-bin allocation
+
+// Grows the bin capacity when the largest bin of an earlier call (read back
+// asynchronously) did not fit; never while capturing.
+void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
+    if (!ctx->bin_pending || capturing(ctx)) return;
+    if (hipEventQuery(ctx->bin_ev) != hipSuccess) { (void)hipGetLastError(); return; }
+    ctx->bin_pending = false;
+    const int32_t need = ctx->pinned[1];
+    int64_t cap = ctx->bin_cap;
+    while (cap < need + need / 4 && cap < ((int64_t)1 << 30)) cap *= 2;
+    while (cap > 1024 && n_records * cap * 4 > kMaxBinBytes) cap /= 2;
+    ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
+}
+
+// One scoring pass: cull, bin, rasterize (+ fused comparison), reduce.
 int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
              float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
     plan(bd, tw, th);
+    for (int s = 0; s < bd.n_scans; ++s)
+        if (bd.s[s].tiles_x * bd.s[s].tiles_y > kMaxTiles || bd.s[s].tiles_x > 256 || bd.s[s].tiles_y > 256)
+            return fail(ctx, RM_ERR_UNSUPPORTED, "%dx%d image needs more than %d tiles of %dx%d", bd.s[s].width,
+                        bd.s[s].height, kMaxTiles, tw, th);
     const int P = bd.n_poses;
     const int64_t C = (mesh->n_tris + kClusterTris - 1) / kClusterTris;
     const int64_t R = total_records(bd);
+    adapt_bin_cap(ctx, R);
     Carve cv;
-    const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P);
+    const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P + 1 + R);   // vis_count, vis_tris, bin_max, bin_count
     const size_t o_vis = cv.take<uint2>((int64_t)P * C);
     const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
     const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
+    const size_t o_bin = cv.take<uint32_t>(R * (int64_t)ctx->bin_cap);
     int rc = ensure_scratch(ctx, cv.off);
     if (rc) return rc;
     int32_t* vis_count = at<int32_t>(ctx, o_cnt);
     int32_t* vis_tris = vis_count + P;
+    int32_t* bin_max = vis_tris + P;
+    int32_t* bin_count = bin_max + 1;
     const void* prep = mesh->clusters;
     if (!prep && C > 0) {
         void* w = at<char>(ctx, o_cb);
@@ -184,7 +217,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     const float* nrm = prep ? reinterpret_cast<const float*>(static_cast<const char*>(prep) +
                                                              prepared_normals_offset(mesh->n_tris))
                             : nullptr;
-    RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P));
+    RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P + 1 + R));
     uint2* vis = at<uint2>(ctx, o_vis);
     RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
     RasterArgs a;
@@ -198,11 +231,16 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     a.T_wc = T_wc;
     a.vis = vis;
     a.vis_count = vis_count;
+    a.bins = at<uint32_t>(ctx, o_bin);
+    a.bin_count = bin_count;
+    a.bin_max = bin_max;
+    a.bin_cap = ctx->bin_cap;
     a.rec = at<float>(ctx, o_rec);
     a.eps = eps;
     a.depth_out = depth_out;
     a.tri_out = tri_out;
     a.cls_out = cls_out;
+    RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
     hipEvent_t pe1 = nullptr;
     if (ctx->profiling && !capturing(ctx)) {
         if (ctx->prof_used == ctx->prof_events.size()) {
@@ -219,6 +257,12 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     if (pe1) RM_HIP(ctx, hipEventRecord(pe1, ctx->stream));
     if (mode != kRender)
         RM_HIP(ctx, launch_reduce(ctx->stream, bd, a.rec, vis_tris, eps, mode == kGrad, out));
+    if (!capturing(ctx) && !ctx->bin_pending) {
+        if (!ctx->bin_ev) RM_HIP(ctx, hipEventCreateWithFlags(&ctx->bin_ev, hipEventDisableTiming));
+        RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, bin_max, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        RM_HIP(ctx, hipEventRecord(ctx->bin_ev, ctx->stream));
+        ctx->bin_pending = true;
+    }
     return RM_OK;
 }
 
@@ -340,6 +384,8 @@ int rm_ctx_destroy(rm_ctx* ctx) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
+        if (ctx->bin_ev) (void)hipEventDestroy(ctx->bin_ev);
+        for (void* r : ctx->retired) (void)hipFree(r);
     }
     delete ctx;
     return RM_OK;
@@ -417,6 +463,7 @@ int rm_graph_end(rm_ctx* ctx, void** graph_exec) {
     hipGraph_t graph = nullptr;
     RM_HIP(ctx, hipStreamEndCapture(ctx->stream, &graph));
     hipGraphExec_t ex = nullptr;
+    ctx->captured = true;
     hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(ctx, RM_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));

@@ -13,6 +13,7 @@ constexpr int kClusterTris = RM_CLUSTER_TRIS;
 constexpr int kQuadBlock = 8;            // meshify emits 8x8 blocks of quads
 constexpr int kRecFields = 40;           // per-(pose, tile) partial record, 4-byte fields
 constexpr int kSnapLimit = 1 << 29;      // |snapped coordinate| must stay below this
+constexpr int kMaxTiles = 4096;          // screen tiles per image (bin-pass LDS tables)
 
 // Per-cluster bounds written by rm_mesh_clusters: world AABB.
 struct ClusterBounds {
@@ -58,6 +59,10 @@ struct RasterArgs {
     const double* T_wc;          // [P][12]
     const uint2* vis;            // [P][n_clusters] (cluster, packed tile rect)
     const int32_t* vis_count;    // [P]
+    uint32_t* bins;              // [n_records][bin_cap] triangle ids per (scan, pose, tile)
+    int32_t* bin_count;          // [n_records] entries appended (may exceed bin_cap)
+    int32_t* bin_max;            // device scalar: largest bin_count of the call
+    int32_t bin_cap;
     float* rec;                  // partial records [n_records][kRecFields]
     float eps;
     // render outputs
@@ -82,6 +87,7 @@ hipError_t launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
 hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds* cb,
                        int32_t n_clusters, const double* T_wc, uint2* vis, int32_t* vis_count,
                        int32_t* vis_tris);
+hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a);
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode);
 hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec,
                          const int32_t* vis_tris, float eps, int grad, double* out);

@@ -21,6 +21,7 @@ struct PoseF {
     float R[3][3];
     double Rd[3][3];      // world -> camera rotation in FP64 (depth planes)
     double t[3];
+    float tf[3];          // camera centre rounded to f32 (binning footprints only)
 };
 
 __device__ __forceinline__ void load_pose(const double* __restrict__ T, PoseF& P) {
@@ -32,6 +33,7 @@ __device__ __forceinline__ void load_pose(const double* __restrict__ T, PoseF& P
             P.R[i][j] = (float)T[4 * j + i];
         }
         P.t[i] = T[4 * i + 3];
+        P.tf[i] = (float)T[4 * i + 3];
     }
 }
 
@@ -105,24 +107,25 @@ struct Tile {
     int x0, y0, x1, y1;   // inclusive pixel range of the tile inside the image
 };
 
-template <typename I>
-__device__ __forceinline__ void raster_loop(uint64_t* keys, int tile_w, const Tile& tl, const int X[3],
-                                            const int Y[3], int px0, int px1, int py0, int py1,
-                                            const WPlane& pl, double cx, double cy, float w_far, uint32_t id) {
-    I E[3], sx[3], sy[3];
+
+// Small (sub-)triangles are rasterized by their own thread over the pixel
+// centres of their bounding box inside the tile (int32 edge functions).
+__device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const Tile& tl, const int X[3],
+                                             const int Y[3], int px0, int px1, int py0, int py1,
+                                             const WPlane& pl, double cx, double cy, float w_far, uint32_t id) {
+    int E[3], sx[3], sy[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int k1 = k == 2 ? 0 : k + 1;
-        const I dx = (I)X[k1] - (I)X[k];
-        const I dy = (I)Y[k1] - (I)Y[k];
+        const int dx = X[k1] - X[k], dy = Y[k1] - Y[k];
         const bool topleft = dy < 0 || (dy == 0 && dx > 0);
-        E[k] = dx * ((I)256 * (I)py0 - (I)Y[k]) - dy * ((I)256 * (I)px0 - (I)X[k]) - (topleft ? 0 : 1);
-        sx[k] = -(I)256 * dy;
-        sy[k] = (I)256 * dx;
+        E[k] = dx * (256 * py0 - Y[k]) - dy * (256 * px0 - X[k]) - (topleft ? 0 : 1);
+        sx[k] = -256 * dy;
+        sy[k] = 256 * dx;
     }
     double wrow = fma(pl.b, (double)py0 - cy, fma(pl.a, (double)px0 - cx, pl.e));
     for (int y = py0; y <= py1; ++y) {
-        I e0 = E[0], e1 = E[1], e2 = E[2];
+        int e0 = E[0], e1 = E[1], e2 = E[2];
         double w = wrow;
         uint64_t* row = keys + (y - tl.y0) * tile_w - tl.x0;
         for (int x = px0; x <= px1; ++x) {
@@ -138,8 +141,71 @@ __device__ __forceinline__ void raster_loop(uint64_t* keys, int tile_w, const Ti
     }
 }
 
-// Setup of one (sub-)triangle of the contract and its rasterization inside the tile.
-__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, const Tile& tl, const CamF& cam,
+// Larger (sub-)triangles are queued in LDS and rasterized row by row by the
+// whole workgroup: one (triangle, row) per thread, an approximate covered
+// span from the three edges, then the exact int64 edge test per pixel.
+constexpr int kBigCap = 2 * kWG;           // a round of kWG triangles queues at most 2 each
+constexpr int kSmallArea = 32;             // bounding-box pixels rasterized in-thread
+
+struct BigQueue {
+    int X[3][kBigCap], Y[3][kBigCap];
+    double pa[kBigCap], pb[kBigCap], pe[kBigCap];
+    uint32_t id[kBigCap];
+    uint32_t box[kBigCap];                 // px0 | px1 << 8 | py0 << 16 | py1 << 24, tile-relative
+    int n;
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void raster_big(uint64_t* keys, BigQueue& q, const Tile& tl, double cx, double cy,
+                                           float w_far) {
+    const int nq = q.n;
+    for (int j = threadIdx.x; j < nq * TH; j += kWG) {
+        const int b = j / TH, r = j - b * TH;
+        const uint32_t box = q.box[b];
+        const int px0 = tl.x0 + (int)(box & 0xff), px1 = tl.x0 + (int)((box >> 8) & 0xff);
+        const int y = tl.y0 + (int)((box >> 16) & 0xff) + r;
+        if (y > tl.y0 + (int)(box >> 24)) continue;
+        int64_t E[3], al[3];
+        float lo = (float)px0, hi = (float)px1;
+        bool empty = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = k == 2 ? 0 : k + 1;
+            const int dx = q.X[k1][b] - q.X[k][b], dy = q.Y[k1][b] - q.Y[k][b];
+            const bool topleft = dy < 0 || (dy == 0 && dx > 0);
+            E[k] = (int64_t)dx * (int64_t)(256 * y - q.Y[k][b]) - (int64_t)dy * (int64_t)(256 * px0 - q.X[k][b]) -
+                   (topleft ? 0 : 1);
+            al[k] = -256 * (int64_t)dy;
+            if (al[k] == 0) {
+                empty |= E[k] < 0;
+            } else {
+                const float xc = (float)px0 - (float)E[k] / (float)al[k];     // where E_k crosses 0
+                if (al[k] > 0) lo = fmaxf(lo, xc); else hi = fminf(hi, xc);
+            }
+        }
+        if (empty || !(lo <= hi + 2.0f)) continue;
+        const int xa = max(px0, (int)floorf(lo) - 1), xb = min(px1, (int)ceilf(hi) + 1);
+        if (xa > xb) continue;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) E[k] += al[k] * (int64_t)(xa - px0);
+        double w = fma(q.pb[b], (double)y - cy, fma(q.pa[b], (double)xa - cx, q.pe[b]));
+        const double wa = q.pa[b];
+        const uint32_t id = q.id[b];
+        uint64_t* row = keys + (y - tl.y0) * TW - tl.x0;
+        for (int x = xa; x <= xb; ++x) {
+            if ((E[0] | E[1] | E[2]) >= 0) {
+                const float wf = (float)w;
+                if (wf >= w_far) atomicMin((unsigned long long*)(row + x), (unsigned long long)pack_key(wf, id));
+            }
+            E[0] += al[0]; E[1] += al[1]; E[2] += al[2];
+            w += wa;
+        }
+    }
+}
+
+// Setup of one (sub-)triangle of the contract: snap, orientation, bounding
+// box inside the tile; small ones are rasterized now, larger ones queued.
+__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, BigQueue& q, const Tile& tl, const CamF& cam,
                                          float3 A, float3 B, float3 C, const WPlane& pl, float w_far,
                                          uint32_t id) {
     int X[3], Y[3];
@@ -156,12 +222,17 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, const Tile&
     const int px0 = max((mnx + 255) >> 8, tl.x0), px1 = min(mxx >> 8, tl.x1);
     const int py0 = max((mny + 255) >> 8, tl.y0), py1 = min(mxy >> 8, tl.y1);
     if (px0 > px1 || py0 > py1) return;
-    if (mxx - mnx < (1 << 14) && mxy - mny < (1 << 14))
-        raster_loop<int32_t>(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far,
-                             id);
-    else
-        raster_loop<int64_t>(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far,
-                             id);
+    if ((px1 - px0 + 1) * (py1 - py0 + 1) <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
+        raster_small(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far, id);
+        return;
+    }
+    const int k = atomicAdd(&q.n, 1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { q.X[i][k] = X[i]; q.Y[i][k] = Y[i]; }
+    q.pa[k] = pl.a; q.pb[k] = pl.b; q.pe[k] = pl.e;
+    q.id[k] = id;
+    q.box[k] = (uint32_t)(px0 - tl.x0) | ((uint32_t)(px1 - tl.x0) << 8) | ((uint32_t)(py0 - tl.y0) << 16) |
+               ((uint32_t)(py1 - tl.y0) << 24);
 }
 
 __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
@@ -169,25 +240,26 @@ __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
 }
 
 // Whole contract for one mesh triangle: transform, far cull, near clip into
-// at most two sub-triangles (same id), setup and rasterization.
-__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, const Tile& tl, const CamF& cam,
-                                                double ifx, double ify, float w_far, const PoseF& P,
-                                                const float* __restrict__ xyz, const int32_t* __restrict__ tri,
-                                                const float* __restrict__ nrm, uint32_t vmax, int64_t t) {
+// at most two sub-triangles (same id), setup and rasterization or queueing.
+__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, BigQueue& q, const Tile& tl,
+                                                const CamF& cam, double ifx, double ify, float w_far,
+                                                const PoseF& P, const float* __restrict__ xyz,
+                                                const int32_t* __restrict__ tri, const float* __restrict__ nrm,
+                                                uint32_t vmax, int64_t t) {
     const uint32_t i0 = min((uint32_t)tri[3 * t], vmax), i1 = min((uint32_t)tri[3 * t + 1], vmax),
                    i2 = min((uint32_t)tri[3 * t + 2], vmax);
-    const float3 V0 = cam_contract(P, xyz[3 * (int64_t)i0], xyz[3 * (int64_t)i0 + 1], xyz[3 * (int64_t)i0 + 2]);
+    const float x0 = xyz[3 * (int64_t)i0], y0 = xyz[3 * (int64_t)i0 + 1], z0 = xyz[3 * (int64_t)i0 + 2];
+    const float3 V0 = cam_contract(P, x0, y0, z0);
     const float3 V1 = cam_contract(P, xyz[3 * (int64_t)i1], xyz[3 * (int64_t)i1 + 1], xyz[3 * (int64_t)i1 + 2]);
     const float3 V2 = cam_contract(P, xyz[3 * (int64_t)i2], xyz[3 * (int64_t)i2 + 1], xyz[3 * (int64_t)i2 + 2]);
     if (V0.z > cam.zf && V1.z > cam.zf && V2.z > cam.zf) return;
     const bool in0 = V0.z >= cam.zn, in1 = V1.z >= cam.zn, in2 = V2.z >= cam.zn;
     const int nin = (int)in0 + (int)in1 + (int)in2;
     if (nin == 0) return;
-    const WPlane pl = depth_plane(P, nrm + 3 * t, xyz[3 * (int64_t)i0], xyz[3 * (int64_t)i0 + 1],
-                                  xyz[3 * (int64_t)i0 + 2], ifx, ify);
+    const WPlane pl = depth_plane(P, nrm + 3 * t, x0, y0, z0, ifx, ify);
     const uint32_t id = (uint32_t)t;
     if (nin == 3) {
-        emit_tri(keys, tile_w, tl, cam, V0, V1, V2, pl, w_far, id);
+        emit_tri(keys, tile_w, q, tl, cam, V0, V1, V2, pl, w_far, id);
     } else if (nin == 2) {
         const int k = !in0 ? 0 : (!in1 ? 1 : 2);          // the outside vertex
         const float3 O = sel3(k, V0, V1, V2);
@@ -195,15 +267,185 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, cons
         const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
         const float3 Pb = clip_point(b, O, cam.zn);
         const float3 Pa = clip_point(a, O, cam.zn);
-        emit_tri(keys, tile_w, tl, cam, a, b, Pb, pl, w_far, id);
-        emit_tri(keys, tile_w, tl, cam, a, Pb, Pa, pl, w_far, id);
+        emit_tri(keys, tile_w, q, tl, cam, a, b, Pb, pl, w_far, id);
+        emit_tri(keys, tile_w, q, tl, cam, a, Pb, Pa, pl, w_far, id);
     } else {
         const int k = in0 ? 0 : (in1 ? 1 : 2);            // the inside vertex
         const float3 I = sel3(k, V0, V1, V2);
         const float3 a = sel3(k == 2 ? 0 : k + 1, V0, V1, V2);
         const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
-        emit_tri(keys, tile_w, tl, cam, I, clip_point(I, a, cam.zn), clip_point(I, b, cam.zn), pl, w_far, id);
+        emit_tri(keys, tile_w, q, tl, cam, I, clip_point(I, a, cam.zn), clip_point(I, b, cam.zn), pl, w_far, id);
     }
+}
+
+// ------------------------------------------------------------------ binning
+
+// Conservative screen footprint of a triangle for binning: approximate
+// float32 camera transform, clip against a plane slightly in front of z_near,
+// projection with the hardware reciprocal; the exact contract is applied
+// later, per tile, so this only has to contain it (2 px margin).
+struct Foot {
+    float u[4], v[4];      // convex polygon; a triangle repeats its last vertex
+};
+
+__device__ __forceinline__ void proj_approx(const CamF& cam, float3 X, float& u, float& v) {
+    const float r = __builtin_amdgcn_rcpf(X.z);
+    u = fmaf(cam.fx * X.x, r, cam.cx);
+    v = fmaf(cam.fy * X.y, r, cam.cy);
+}
+
+__device__ __forceinline__ float3 clip_approx(float3 I, float3 O, float zc) {
+    const float t = (zc - I.z) / (O.z - I.z);
+    return make_float3(fmaf(t, O.x - I.x, I.x), fmaf(t, O.y - I.y, I.y), zc);
+}
+
+__device__ __forceinline__ bool footprint(const PoseF& P, const CamF& cam, float3 W0, float3 W1, float3 W2,
+                                          Foot& f) {
+    float3 V[3];
+    const float3 Wv[3] = {W0, W1, W2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float d0 = Wv[k].x - P.tf[0], d1 = Wv[k].y - P.tf[1], d2 = Wv[k].z - P.tf[2];
+        V[k].x = fmaf(P.R[0][2], d2, fmaf(P.R[0][1], d1, P.R[0][0] * d0));
+        V[k].y = fmaf(P.R[1][2], d2, fmaf(P.R[1][1], d1, P.R[1][0] * d0));
+        V[k].z = fmaf(P.R[2][2], d2, fmaf(P.R[2][1], d1, P.R[2][0] * d0));
+    }
+    const float s = V[0].x + V[0].y + V[0].z + V[1].x + V[1].y + V[1].z + V[2].x + V[2].y + V[2].z;
+    if (!isfinite(s)) return false;
+    const float znp = cam.zn * (1.0f - 1e-4f), zfp = cam.zf * (1.0f + 1e-4f);
+    const bool in0 = V[0].z >= znp, in1 = V[1].z >= znp, in2 = V[2].z >= znp;
+    const int nin = (int)in0 + (int)in1 + (int)in2;
+    if (nin == 0) return false;
+    if (V[0].z > zfp && V[1].z > zfp && V[2].z > zfp) return false;
+    float3 Q0, Q1, Q2, Q3;
+    if (nin == 3) {
+        Q0 = V[0]; Q1 = V[1]; Q2 = V[2]; Q3 = V[2];
+    } else if (nin == 2) {
+        const int k = !in0 ? 0 : (!in1 ? 1 : 2);
+        const float3 O = sel3(k, V[0], V[1], V[2]);
+        const float3 a = sel3(k == 2 ? 0 : k + 1, V[0], V[1], V[2]);
+        const float3 b = sel3(k == 0 ? 2 : k - 1, V[0], V[1], V[2]);
+        Q0 = a; Q1 = b; Q2 = clip_approx(b, O, znp); Q3 = clip_approx(a, O, znp);
+    } else {
+        const int k = in0 ? 0 : (in1 ? 1 : 2);
+        const float3 I = sel3(k, V[0], V[1], V[2]);
+        const float3 a = sel3(k == 2 ? 0 : k + 1, V[0], V[1], V[2]);
+        const float3 b = sel3(k == 0 ? 2 : k - 1, V[0], V[1], V[2]);
+        Q0 = I; Q1 = clip_approx(I, a, znp); Q2 = clip_approx(I, b, znp); Q3 = Q2;
+    }
+    proj_approx(cam, Q0, f.u[0], f.v[0]);
+    proj_approx(cam, Q1, f.u[1], f.v[1]);
+    proj_approx(cam, Q2, f.u[2], f.v[2]);
+    proj_approx(cam, Q3, f.u[3], f.v[3]);
+    return true;
+}
+
+// True unless the footprint polygon certainly misses the rectangle of pixel
+// centres [x0, x1] x [y0, y1] (widened by 2 px).
+__device__ __forceinline__ bool foot_hits(const Foot& f, float area2, float x0, float x1, float y0, float y1) {
+    x0 -= 2.0f; y0 -= 2.0f; x1 += 2.0f; y1 += 2.0f;
+    const float sg = area2 > 0.0f ? 1.0f : -1.0f;
+    bool hit = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        const float A = -sg * (f.v[j] - f.v[i]), B = sg * (f.u[j] - f.u[i]);
+        const float xs = A > 0.0f ? x1 : x0, ys = B > 0.0f ? y1 : y0;
+        const float e = A * (xs - f.u[i]) + B * (ys - f.v[i]);
+        const float tol = 1e-4f * (fabsf(A) * fabsf(xs - f.u[i]) + fabsf(B) * fabsf(ys - f.v[i])) + 1e-6f;
+        hit &= !(e < -tol);
+    }
+    return hit;
+}
+
+__device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
+    int s = 0;
+    while (s + 1 < bd.n_scans && pose >= bd.s[s + 1].pose_off) ++s;
+    return s;
+}
+
+// One workgroup per (pose, visible cluster): each thread bins its triangle
+// into the (pose, tile) bins its footprint touches.  Tile counts are
+// aggregated in LDS over the cluster's tile rectangle, then reserved with
+// one global atomic per (workgroup, tile).
+template <int TW, int TH>
+__global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
+    __shared__ uint32_t tcnt[kMaxTiles];
+    __shared__ uint32_t tbase[kMaxTiles];
+    const int pose = blockIdx.y;
+    const int k = blockIdx.x;
+    if (k >= a.vis_count[pose]) return;
+    const ScanDesc& sd = bd.s[pose_scan(bd, pose)];
+    const CamF cam{sd.fx, sd.fy, sd.cx, sd.cy, sd.z_near, sd.z_far, sd.width, sd.height};
+    const uint2 e = a.vis[(int64_t)pose * a.n_clusters + k];
+    const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
+    const int rw = rx1 - rx0 + 1, nrect = rw * (ry1 - ry0 + 1);
+    for (int i = threadIdx.x; i < nrect; i += kWG) tcnt[i] = 0;
+    PoseF P;
+    load_pose(a.T_wc + 12 * (int64_t)pose, P);
+    const int64_t t = (int64_t)e.x * kClusterTris + threadIdx.x;
+    Foot f;
+    bool ok = false;
+    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+    float area2 = 0.0f;
+    if (t < a.n_tris) {
+        const uint32_t i0 = min((uint32_t)a.tri[3 * t], a.vmax), i1 = min((uint32_t)a.tri[3 * t + 1], a.vmax),
+                       i2 = min((uint32_t)a.tri[3 * t + 2], a.vmax);
+        const float3 W0 = make_float3(a.xyz[3 * (int64_t)i0], a.xyz[3 * (int64_t)i0 + 1], a.xyz[3 * (int64_t)i0 + 2]);
+        const float3 W1 = make_float3(a.xyz[3 * (int64_t)i1], a.xyz[3 * (int64_t)i1 + 1], a.xyz[3 * (int64_t)i1 + 2]);
+        const float3 W2 = make_float3(a.xyz[3 * (int64_t)i2], a.xyz[3 * (int64_t)i2 + 1], a.xyz[3 * (int64_t)i2 + 2]);
+        ok = footprint(P, cam, W0, W1, W2, f);
+        if (ok) {
+            float umin = f.u[0], umax = f.u[0], vmin = f.v[0], vmax = f.v[0];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = (i + 1) & 3;
+                umin = fminf(umin, f.u[i]); umax = fmaxf(umax, f.u[i]);
+                vmin = fminf(vmin, f.v[i]); vmax = fmaxf(vmax, f.v[i]);
+                area2 += f.u[i] * f.v[j] - f.u[j] * f.v[i];
+            }
+            umin -= 2.0f; vmin -= 2.0f; umax += 2.0f; vmax += 2.0f;
+            const float W1f = (float)(cam.W - 1), H1f = (float)(cam.H - 1);
+            ok = umax >= 0.0f && vmax >= 0.0f && umin <= W1f && vmin <= H1f;
+            if (ok) {
+                tx0 = max((int)fmaxf(umin, 0.0f) / TW, rx0);
+                tx1 = min((int)fminf(umax, W1f) / TW, rx1);
+                ty0 = max((int)fmaxf(vmin, 0.0f) / TH, ry0);
+                ty1 = min((int)fminf(vmax, H1f) / TH, ry1);
+            }
+        }
+    }
+    const bool test_tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > 2 && fabsf(area2) > 1e-3f;
+    __syncthreads();
+    if (ok)
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx)
+                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
+                                             (float)(ty * TH + TH - 1)))
+                    atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], 1u);
+    __syncthreads();
+    const int pl = pose - sd.pose_off;
+    const int ntile = sd.tiles_x * sd.tiles_y;
+    const int64_t rec0 = sd.rec_off + (int64_t)pl * ntile;
+    for (int i = threadIdx.x; i < nrect; i += kWG) {
+        const uint32_t n = tcnt[i];
+        if (n) {
+            const int tile = (ry0 + i / rw) * sd.tiles_x + rx0 + i % rw;
+            tbase[i] = (uint32_t)atomicAdd(a.bin_count + rec0 + tile, (int)n);
+            tcnt[i] = 0;
+        }
+    }
+    __syncthreads();
+    if (ok)
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx)
+                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
+                                             (float)(ty * TH + TH - 1))) {
+                    const int i = (ty - ry0) * rw + (tx - rx0);
+                    const uint32_t slot = tbase[i] + atomicAdd(&tcnt[i], 1u);
+                    if (slot < (uint32_t)a.bin_cap)
+                        a.bins[(rec0 + ty * sd.tiles_x + tx) * (int64_t)a.bin_cap + slot] = (uint32_t)t;
+                }
 }
 
 // ------------------------------------------------------------------ per-pixel comparison
@@ -262,6 +504,7 @@ __device__ __forceinline__ bool decode_item(const BatchDesc& bd, ItemInfo& it) {
 template <int TW, int TH, int MODE>
 __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
     __shared__ uint64_t keys[TW * TH];
+    __shared__ BigQueue q;
     __shared__ uint32_t clist[kWG];
     __shared__ int ccount;
     __shared__ float red[kWG / 64][kRecFields];
@@ -272,6 +515,7 @@ __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
     CamF cam{sd.fx, sd.fy, sd.cx, sd.cy, sd.z_near, sd.z_far, sd.width, sd.height};
     const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
     const double difx = 1.0 / (double)cam.fx, dify = 1.0 / (double)cam.fy;
+    const double dcx = (double)cam.cx, dcy = (double)cam.cy;
     const float w_far = 1.0f / cam.zf;
     const int tx = it.tile % sd.tiles_x, ty = it.tile / sd.tiles_x;
     Tile tl;
@@ -283,34 +527,56 @@ __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
 
     PoseF P;
     load_pose(a.T_wc + 12 * (int64_t)it.pose, P);
-    const int nvis = a.vis_count[it.pose];
-    const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
-    const uint32_t my_tile = (uint32_t)tx | ((uint32_t)ty << 16);
-    (void)my_tile;
+    const int nbin = a.bin_count[it.rec];
+    if (tid == 0) atomicMax(a.bin_max, nbin);
 
-    for (int base = 0; base < nvis; base += kWG) {
-        if (tid == 0) ccount = 0;
-        __syncthreads();
-        bool take = false;
-        uint32_t cid = 0;
-        if (base + tid < nvis) {
-            const uint2 e = vis[base + tid];
-            const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
-            take = tx >= rx0 && tx <= rx1 && ty >= ry0 && ty <= ry1;
-            cid = e.x;
+    if (nbin <= a.bin_cap) {
+        // the (pose, tile) bin: every triangle whose footprint touches the tile
+        const uint32_t* bin = a.bins + it.rec * (int64_t)a.bin_cap;
+        for (int base = 0; base < nbin; base += kWG) {
+            if (tid == 0) q.n = 0;
+            __syncthreads();
+            if (base + tid < nbin)
+                raster_triangle(keys, TW, q, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax,
+                                (int64_t)bin[base + tid]);
+            __syncthreads();
+            raster_big<TW, TH>(keys, q, tl, dcx, dcy, w_far);
+            __syncthreads();
         }
-        const uint64_t m = __ballot(take);
-        int wbase = 0;
-        if (lane == 0 && m) wbase = atomicAdd(&ccount, __popcll(m));
-        wbase = __shfl(wbase, 0);
-        if (take) clist[wbase + __popcll(m & ((1ull << lane) - 1ull))] = cid;
-        __syncthreads();
-        const int nc = ccount;
-        for (int k = 0; k < nc; ++k) {
-            const int64_t t = (int64_t)clist[k] * kClusterTris + tid;
-            if (t < a.n_tris) raster_triangle(keys, TW, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax, t);
+    } else {
+        // bin overflow: every triangle of every visible cluster whose tile
+        // rectangle holds this tile (slower, same result)
+        const int nvis = a.vis_count[it.pose];
+        const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
+        for (int base = 0; base < nvis; base += kWG) {
+            if (tid == 0) ccount = 0;
+            __syncthreads();
+            bool take = false;
+            uint32_t cid = 0;
+            if (base + tid < nvis) {
+                const uint2 e = vis[base + tid];
+                const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
+                take = tx >= rx0 && tx <= rx1 && ty >= ry0 && ty <= ry1;
+                cid = e.x;
+            }
+            const uint64_t m = __ballot(take);
+            int wbase = 0;
+            if (lane == 0 && m) wbase = atomicAdd(&ccount, __popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (take) clist[wbase + __popcll(m & ((1ull << lane) - 1ull))] = cid;
+            __syncthreads();
+            const int nc = ccount;
+            for (int k = 0; k < nc; ++k) {
+                if (tid == 0) q.n = 0;
+                __syncthreads();
+                const int64_t t = (int64_t)clist[k] * kClusterTris + tid;
+                if (t < a.n_tris)
+                    raster_triangle(keys, TW, q, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax, t);
+                __syncthreads();
+                raster_big<TW, TH>(keys, q, tl, dcx, dcy, w_far);
+                __syncthreads();
+            }
         }
-        __syncthreads();
     }
 
     // ---------------------------------------------------------------- resolve
@@ -572,6 +838,13 @@ __global__ void k_reduce(BatchDesc bd, const float* __restrict__ rec, const int3
 }
 
 template <int TW, int TH>
+hipError_t launch_bin_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
+    const dim3 grid((unsigned)(a.n_clusters > 0 ? a.n_clusters : 1), (unsigned)bd.n_poses);
+    hipLaunchKernelGGL((k_bin<TW, TH>), grid, dim3(kWG), 0, st, bd, a);
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
 hipError_t launch_raster_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {
     const int64_t chunk = (bd.n_items + 7) / 8;
     const dim3 grid((unsigned)(chunk * 8));
@@ -589,6 +862,13 @@ hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds*
     const dim3 grid((unsigned)((n_clusters + kWG - 1) / kWG), (unsigned)bd.n_poses);
     hipLaunchKernelGGL(k_cull, grid, dim3(kWG), 0, st, bd, cb, n_clusters, T_wc, vis, vis_count, vis_tris);
     return hipGetLastError();
+}
+
+hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
+    if (bd.n_items == 0 || a.n_clusters == 0) return hipSuccess;
+    if (bd.tile_w == 16 && bd.tile_h == 16) return launch_bin_t<16, 16>(st, bd, a);
+    if (bd.tile_w == 64 && bd.tile_h == 32) return launch_bin_t<64, 32>(st, bd, a);
+    return launch_bin_t<32, 32>(st, bd, a);
 }
 
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {
