@@ -146,7 +146,7 @@ int rm_ctx_set_stream(rm_ctx* ctx, void* stream);
 const char* rm_last_error(const rm_ctx* ctx);
 /* Selects the screen-tile shape of the rasterizer: tile_w x tile_h one of
  * 16x16, 32x32, 64x32; (0, 0) restores automatic choice (autotuned when
- * rm_autotune is on, 32x32 otherwise).  Results do not depend on it. */
+ * rm_autotune is on, 64x32 otherwise).  Results do not depend on it. */
 int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
 /* Turns the tile autotuner on or off.  When on, the first call for a new
  * (image size, pose count, triangle count) times every tile shape on the

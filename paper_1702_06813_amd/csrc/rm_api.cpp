@@ -178,7 +178,7 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
     ctx->bin_pending = false;
     const int32_t need = ctx->pinned[1];
     int64_t cap = ctx->bin_cap;
-    while (cap < need + need / 4 && cap < ((int64_t)1 << 30)) cap *= 2;
+    while (cap < need + need / 4 && cap < ((int64_t)1 << 24)) cap *= 2;
     while (cap > 1024 && n_records * cap * 4 > kMaxBinBytes) cap /= 2;
     ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
 }
@@ -196,7 +196,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     const int64_t R = total_records(bd);
     adapt_bin_cap(ctx, R);
     Carve cv;
-    const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P + 1 + R);   // vis_count, vis_tris, bin_max, bin_count
+    const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P + 1 + 2 * R);   // vis_count, vis_tris, bin_max, bin fills
     const size_t o_vis = cv.take<uint2>((int64_t)P * C);
     const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
     const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
@@ -206,7 +206,8 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     int32_t* vis_count = at<int32_t>(ctx, o_cnt);
     int32_t* vis_tris = vis_count + P;
     int32_t* bin_max = vis_tris + P;
-    int32_t* bin_count = bin_max + 1;
+    int32_t* bin_small = bin_max + 1;
+    int32_t* bin_big = bin_small + R;
     const void* prep = mesh->clusters;
     if (!prep && C > 0) {
         void* w = at<char>(ctx, o_cb);
@@ -217,7 +218,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     const float* nrm = prep ? reinterpret_cast<const float*>(static_cast<const char*>(prep) +
                                                              prepared_normals_offset(mesh->n_tris))
                             : nullptr;
-    RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P + 1 + R));
+    RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P + 1 + 2 * R));
     uint2* vis = at<uint2>(ctx, o_vis);
     RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
     RasterArgs a;
@@ -232,7 +233,8 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     a.vis = vis;
     a.vis_count = vis_count;
     a.bins = at<uint32_t>(ctx, o_bin);
-    a.bin_count = bin_count;
+    a.bin_small = bin_small;
+    a.bin_big = bin_big;
     a.bin_max = bin_max;
     a.bin_cap = ctx->bin_cap;
     a.rec = at<float>(ctx, o_rec);
@@ -277,7 +279,7 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
         return run_pass(ctx, mesh, bd, it->second.first, it->second.second, mode, T_wc, eps, out, depth_out,
                         tri_out, cls_out);
     if (!ctx->autotune || capturing(ctx))
-        return run_pass(ctx, mesh, bd, 32, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out);
+        return run_pass(ctx, mesh, bd, 64, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out);
     if (!ctx->ev0) {
         RM_HIP(ctx, hipEventCreate(&ctx->ev0));
         RM_HIP(ctx, hipEventCreate(&ctx->ev1));
@@ -422,7 +424,7 @@ int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int
         auto it = ctx->tuned.find(std::make_tuple(width, height, n_poses, n_tris, mode));
         if (it != ctx->tuned.end()) { *tile_w = it->second.first; *tile_h = it->second.second; return RM_OK; }
     }
-    *tile_w = 32;
+    *tile_w = 64;
     *tile_h = 32;
     return RM_OK;
 }
@@ -572,7 +574,7 @@ int rm_render_depth(rm_ctx* ctx, const rm_mesh* mesh, rm_camera cam, const doubl
     bd.s[0].pose_off = 0;
     bd.s[0].n_poses = n_poses;
     DeviceGuard g(ctx->device);
-    const int tw = ctx->tile_w ? ctx->tile_w : 32, th = ctx->tile_w ? ctx->tile_h : 32;
+    const int tw = ctx->tile_w ? ctx->tile_w : 64, th = ctx->tile_w ? ctx->tile_h : 32;
     return run_pass(ctx, mesh, bd, tw, th, kRender, T_wc, 1.0f, nullptr, depth_out, tri_out, cls_out);
 }
 

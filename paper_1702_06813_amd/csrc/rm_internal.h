@@ -13,7 +13,7 @@ constexpr int kClusterTris = RM_CLUSTER_TRIS;
 constexpr int kQuadBlock = 8;            // meshify emits 8x8 blocks of quads
 constexpr int kRecFields = 40;           // per-(pose, tile) partial record, 4-byte fields
 constexpr int kSnapLimit = 1 << 29;      // |snapped coordinate| must stay below this
-constexpr int kMaxTiles = 4096;          // screen tiles per image (bin-pass LDS tables)
+constexpr int kMaxTiles = 2048;          // screen tiles per image (bin-pass LDS tables)
 
 // Per-cluster bounds written by rm_mesh_clusters: world AABB.
 struct ClusterBounds {
@@ -59,9 +59,11 @@ struct RasterArgs {
     const double* T_wc;          // [P][12]
     const uint2* vis;            // [P][n_clusters] (cluster, packed tile rect)
     const int32_t* vis_count;    // [P]
-    uint32_t* bins;              // [n_records][bin_cap] triangle ids per (scan, pose, tile)
-    int32_t* bin_count;          // [n_records] entries appended (may exceed bin_cap)
-    int32_t* bin_max;            // device scalar: largest bin_count of the call
+    uint32_t* bins;              // [n_records][bin_cap] triangle ids per (scan, pose, tile):
+                                 // small footprints from the front, large ones from the back
+    int32_t* bin_small;          // [n_records] small entries appended (may exceed bin_cap)
+    int32_t* bin_big;            // [n_records] large entries appended
+    int32_t* bin_max;            // device scalar: largest bin fill of the call
     int32_t bin_cap;
     float* rec;                  // partial records [n_records][kRecFields]
     float eps;

@@ -5,6 +5,8 @@
 //
 // The z-buffer R(T(X)) is Eq. (1) of the paper; the per-pixel rules are its
 // Table I (Sec. IV-B); the total error is their sum over pixels (Sec. IV-B).
+#include <algorithm>
+
 #include "rm_internal.h"
 
 namespace rm {
@@ -19,7 +21,6 @@ namespace {
 // fmaf in the order z-, y-, x-column.
 struct PoseF {
     float R[3][3];
-    double Rd[3][3];      // world -> camera rotation in FP64 (depth planes)
     double t[3];
     float tf[3];          // camera centre rounded to f32 (binning footprints only)
 };
@@ -28,10 +29,7 @@ __device__ __forceinline__ void load_pose(const double* __restrict__ T, PoseF& P
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            P.Rd[i][j] = T[4 * j + i];
-            P.R[i][j] = (float)T[4 * j + i];
-        }
+        for (int j = 0; j < 3; ++j) P.R[i][j] = (float)T[4 * j + i];
         P.t[i] = T[4 * i + 3];
         P.tf[i] = (float)T[4 * i + 3];
     }
@@ -93,9 +91,11 @@ __device__ __forceinline__ WPlane depth_plane(const PoseF& P, const float* __res
     const double n0 = nw[0], n1 = nw[1], n2 = nw[2];
     const double c = n0 * ((double)x0 - P.t[0]) + n1 * ((double)y0 - P.t[1]) + n2 * ((double)z0 - P.t[2]);
     const double ic = 1.0 / c;
-    const double nx = P.Rd[0][0] * n0 + P.Rd[0][1] * n1 + P.Rd[0][2] * n2;
-    const double ny = P.Rd[1][0] * n0 + P.Rd[1][1] * n1 + P.Rd[1][2] * n2;
-    const double nz = P.Rd[2][0] * n0 + P.Rd[2][1] * n1 + P.Rd[2][2] * n2;
+    // camera-frame normal with the f32-rounded rotation (a 6e-8 rotation of the
+    // plane about its anchor vertex, far below the depth tolerance)
+    const double nx = (double)P.R[0][0] * n0 + (double)P.R[0][1] * n1 + (double)P.R[0][2] * n2;
+    const double ny = (double)P.R[1][0] * n0 + (double)P.R[1][1] * n1 + (double)P.R[1][2] * n2;
+    const double nz = (double)P.R[2][0] * n0 + (double)P.R[2][1] * n1 + (double)P.R[2][2] * n2;
     WPlane p;
     p.a = nx * ic * ifx;
     p.b = ny * ic * ify;
@@ -129,9 +129,10 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
         double w = wrow;
         uint64_t* row = keys + (y - tl.y0) * tile_w - tl.x0;
         for (int x = px0; x <= px1; ++x) {
-            if ((e0 | e1 | e2) >= 0) {
+            {   // branch-free: an uncovered pixel offers the empty key, which changes nothing
                 const float wf = (float)w;
-                if (wf >= w_far) atomicMin((unsigned long long*)(row + x), (unsigned long long)pack_key(wf, id));
+                const bool cov = ((e0 | e1 | e2) >= 0) & (wf >= w_far);
+                atomicMin((unsigned long long*)(row + x), cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
             }
             e0 += sx[0]; e1 += sx[1]; e2 += sx[2];
             w += pl.a;
@@ -141,71 +142,141 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
     }
 }
 
-// Larger (sub-)triangles are queued in LDS and rasterized row by row by the
-// whole workgroup: one (triangle, row) per thread, an approximate covered
-// span from the three edges, then the exact int64 edge test per pixel.
-constexpr int kBigCap = 2 * kWG;           // a round of kWG triangles queues at most 2 each
-constexpr int kSmallArea = 32;             // bounding-box pixels rasterized in-thread
+// Larger (sub-)triangles are queued in LDS and rasterized by the whole
+// workgroup in jobs of kBand rows: a job brackets the covered span of each of
+// its rows between the three edge crossings (FP64, exact to far below a
+// pixel) and gives only pixel centres inside it the exact int64 edge test.
+constexpr int kQCap = kWG + 32;            // queued sub-triangles per round (more go in-thread)
+constexpr int kBand = 4;                   // rows per job
+constexpr int kSmallArea = 32;             // bounding-box pixels rasterized by the owning thread
+constexpr int kFatPixels = 256;            // estimated covered pixels that send a triangle to the fat path
+constexpr int kFatCap = 32;
 
+constexpr int kMaxBands = 8;              // tile height / kBand for the tallest tile (32 rows)
 struct BigQueue {
-    int X[3][kBigCap], Y[3][kBigCap];
-    double pa[kBigCap], pb[kBigCap], pe[kBigCap];
-    uint32_t id[kBigCap];
-    uint32_t box[kBigCap];                 // px0 | px1 << 8 | py0 << 16 | py1 << 24, tile-relative
+    int X[3][kQCap], Y[3][kQCap];          // snapped vertices relative to the tile origin (1/256 px)
+    double m[3][kQCap];                    // edge slope dx/dy (0 for horizontal edges)
+    double pa[kQCap], pb[kQCap], pe[kQCap];
+    uint32_t id[kQCap];
+    uint32_t box[kQCap];                   // tile-relative px0 | px1 << 8 | py0 << 16 | py1 << 24
+    uint16_t job[kQCap * kMaxBands];       // queued entry << 4 | band, only bands the entry covers
+    int n, njobs;
+};
+
+// Triangles that cover much of the tile: one pixel centre per thread at a time.
+struct FatQueue {
+    int64_t E[3][kFatCap];                 // edge functions at (px0, py0)
+    int dx[3][kFatCap], dy[3][kFatCap];
+    double pa[kFatCap], pb[kFatCap], pe[kFatCap];
+    uint32_t id[kFatCap];
+    uint32_t box[kFatCap];
     int n;
 };
 
-template <int TW, int TH>
-__device__ __forceinline__ void raster_big(uint64_t* keys, BigQueue& q, const Tile& tl, double cx, double cy,
-                                           float w_far) {
-    const int nq = q.n;
-    for (int j = threadIdx.x; j < nq * TH; j += kWG) {
-        const int b = j / TH, r = j - b * TH;
-        const uint32_t box = q.box[b];
-        const int px0 = tl.x0 + (int)(box & 0xff), px1 = tl.x0 + (int)((box >> 8) & 0xff);
-        const int y = tl.y0 + (int)((box >> 16) & 0xff) + r;
-        if (y > tl.y0 + (int)(box >> 24)) continue;
-        int64_t E[3], al[3];
-        float lo = (float)px0, hi = (float)px1;
+// Rows r0..r1 (tile-relative) of one sub-triangle with tile-relative snapped
+// vertices (X, Y), edge slopes m, depth plane and tile-relative column range.
+__device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Tile& tl, const int X[3],
+                                            const int Y[3], const double m[3], double pa, double pb, double pe,
+                                            uint32_t id, int bx0, int bx1, int r0, int r1, double cx, double cy,
+                                            float w_far) {
+    int64_t E[3];
+    int dx[3], dy[3];
+    double xc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        dx[k] = X[k1] - X[k];
+        dy[k] = Y[k1] - Y[k];
+        const bool topleft = dy[k] < 0 || (dy[k] == 0 && dx[k] > 0);
+        E[k] = (int64_t)dx[k] * (int64_t)(256 * r0 - Y[k]) - (int64_t)dy[k] * (int64_t)(256 * bx0 - X[k]) -
+               (topleft ? 0 : 1);
+        xc[k] = ((double)X[k] + (double)(256 * r0 - Y[k]) * m[k]) * (1.0 / 256.0);   // crossing on row r0
+    }
+    double wrow = fma(pb, (double)(tl.y0 + r0) - cy, fma(pa, (double)(tl.x0 + bx0) - cx, pe));
+    for (int r = r0; r <= r1; ++r) {
+        double lo = (double)bx0, hi = (double)bx1;
         bool empty = false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int k1 = k == 2 ? 0 : k + 1;
-            const int dx = q.X[k1][b] - q.X[k][b], dy = q.Y[k1][b] - q.Y[k][b];
-            const bool topleft = dy < 0 || (dy == 0 && dx > 0);
-            E[k] = (int64_t)dx * (int64_t)(256 * y - q.Y[k][b]) - (int64_t)dy * (int64_t)(256 * px0 - q.X[k][b]) -
-                   (topleft ? 0 : 1);
-            al[k] = -256 * (int64_t)dy;
-            if (al[k] == 0) {
-                empty |= E[k] < 0;
-            } else {
-                const float xc = (float)px0 - (float)E[k] / (float)al[k];     // where E_k crosses 0
-                if (al[k] > 0) lo = fmaxf(lo, xc); else hi = fminf(hi, xc);
+            if (dy[k] < 0) lo = fmax(lo, xc[k]);
+            else if (dy[k] > 0) hi = fmin(hi, xc[k]);
+            else empty |= E[k] < 0;                 // horizontal edge: the whole row is in or out
+        }
+        const int xa = max(bx0, (int)ceil(lo - 1e-6)), xb = min(bx1, (int)floor(hi + 1e-6));
+        if (!empty && xa <= xb) {
+            int64_t e0 = E[0] - 256 * (int64_t)dy[0] * (xa - bx0);
+            int64_t e1 = E[1] - 256 * (int64_t)dy[1] * (xa - bx0);
+            int64_t e2 = E[2] - 256 * (int64_t)dy[2] * (xa - bx0);
+            double w = fma(pa, (double)(xa - bx0), wrow);
+            uint64_t* row = keys + r * tile_w;
+            for (int x = xa; x <= xb; ++x) {
+                {
+                    const float wf = (float)w;
+                    const bool cov = ((e0 | e1 | e2) >= 0) & (wf >= w_far);
+                    atomicMin((unsigned long long*)(row + x), cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
+                }
+                e0 -= 256 * (int64_t)dy[0]; e1 -= 256 * (int64_t)dy[1]; e2 -= 256 * (int64_t)dy[2];
+                w += pa;
             }
         }
-        if (empty || !(lo <= hi + 2.0f)) continue;
-        const int xa = max(px0, (int)floorf(lo) - 1), xb = min(px1, (int)ceilf(hi) + 1);
-        if (xa > xb) continue;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) E[k] += al[k] * (int64_t)(xa - px0);
-        double w = fma(q.pb[b], (double)y - cy, fma(q.pa[b], (double)xa - cx, q.pe[b]));
-        const double wa = q.pa[b];
-        const uint32_t id = q.id[b];
-        uint64_t* row = keys + (y - tl.y0) * TW - tl.x0;
-        for (int x = xa; x <= xb; ++x) {
-            if ((E[0] | E[1] | E[2]) >= 0) {
-                const float wf = (float)w;
-                if (wf >= w_far) atomicMin((unsigned long long*)(row + x), (unsigned long long)pack_key(wf, id));
+        for (int k = 0; k < 3; ++k) { E[k] += 256 * (int64_t)dx[k]; xc[k] += m[k]; }
+        wrow += pb;
+    }
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const Tile& tl, double cx, double cy,
+                                             float w_far) {
+    const int nj = q.njobs;
+    for (int j = threadIdx.x; j < nj; j += kWG) {
+        const int rec = q.job[j];
+        const int b = rec >> 4, band = rec & 15;
+        const uint32_t box = q.box[b];
+        const int by0 = (int)((box >> 16) & 0xff), by1 = (int)(box >> 24);
+        const int r0 = max(by0, band * kBand), r1 = min(by1, band * kBand + kBand - 1);
+        const int X[3] = {q.X[0][b], q.X[1][b], q.X[2][b]};
+        const int Y[3] = {q.Y[0][b], q.Y[1][b], q.Y[2][b]};
+        const double m[3] = {q.m[0][b], q.m[1][b], q.m[2][b]};
+        raster_rows(keys, TW, tl, X, Y, m, q.pa[b], q.pb[b], q.pe[b], q.id[b], (int)(box & 0xff),
+                    (int)((box >> 8) & 0xff), r0, r1, cx, cy, w_far);
+    }
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Tile& tl, double cx, double cy,
+                                           float w_far) {
+    const int nq = min(q.n, kFatCap);
+    for (int b = 0; b < nq; ++b) {
+        const uint32_t box = q.box[b];
+        const int bx0 = (int)(box & 0xff), bx1 = (int)((box >> 8) & 0xff);
+        const int by0 = (int)((box >> 16) & 0xff), by1 = (int)(box >> 24);
+        for (int p = threadIdx.x + by0 * TW; p < (by1 + 1) * TW; p += kWG) {
+            const int y = p / TW, x = p % TW;              // TW is a power of two
+            if (x < bx0 || x > bx1) continue;
+            const int ry = y - by0, rx = x - bx0;
+            bool in = true;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t e = q.E[k][b] + 256 * ((int64_t)q.dx[k][b] * ry - (int64_t)q.dy[k][b] * rx);
+                in &= e >= 0;
             }
-            E[0] += al[0]; E[1] += al[1]; E[2] += al[2];
-            w += wa;
+            if (!in) continue;
+            const float wf = (float)fma(q.pb[b], (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
+            if (wf >= w_far)
+                atomicMin((unsigned long long*)(keys + y * TW + x), (unsigned long long)pack_key(wf, q.id[b]));
         }
     }
 }
 
 // Setup of one (sub-)triangle of the contract: snap, orientation, bounding
-// box inside the tile; small ones are rasterized now, larger ones queued.
-__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, BigQueue& q, const Tile& tl, const CamF& cam,
+// box inside the tile, then the rasterization path by size.
+struct Queues {
+    BigQueue big;
+    FatQueue fat;
+};
+
+__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const Tile& tl, const CamF& cam,
                                          float3 A, float3 B, float3 C, const WPlane& pl, float w_far,
                                          uint32_t id) {
     int X[3], Y[3];
@@ -222,17 +293,65 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, BigQueue& q
     const int px0 = max((mnx + 255) >> 8, tl.x0), px1 = min(mxx >> 8, tl.x1);
     const int py0 = max((mny + 255) >> 8, tl.y0), py1 = min(mxy >> 8, tl.y1);
     if (px0 > px1 || py0 > py1) return;
-    if ((px1 - px0 + 1) * (py1 - py0 + 1) <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
+    const int boxpx = (px1 - px0 + 1) * (py1 - py0 + 1);
+    const uint32_t box = (uint32_t)(px0 - tl.x0) | ((uint32_t)(px1 - tl.x0) << 8) | ((uint32_t)(py0 - tl.y0) << 16) |
+                         ((uint32_t)(py1 - tl.y0) << 24);
+    if (boxpx <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
         raster_small(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far, id);
         return;
     }
-    const int k = atomicAdd(&q.n, 1);
+    // fat: many covered pixels in the tile and thick (2 area / longest edge > 8 px)
+    double l2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { q.X[i][k] = X[i]; q.Y[i][k] = Y[i]; }
-    q.pa[k] = pl.a; q.pb[k] = pl.b; q.pe[k] = pl.e;
-    q.id[k] = id;
-    q.box[k] = (uint32_t)(px0 - tl.x0) | ((uint32_t)(px1 - tl.x0) << 8) | ((uint32_t)(py0 - tl.y0) << 16) |
-               ((uint32_t)(py1 - tl.y0) << 24);
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = i == 2 ? 0 : i + 1;
+        const double ex = (double)(X[i1] - X[i]), ey = (double)(Y[i1] - Y[i]);
+        l2 = fmax(l2, ex * ex + ey * ey);
+    }
+    const double area_px = (double)area * (0.5 / 65536.0);
+    if (boxpx > kFatPixels && area_px > kFatPixels && (double)area * (double)area > 64.0 * 65536.0 * l2) {
+        const int k = atomicAdd(&Q.fat.n, 1);
+        if (k < kFatCap) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int i1 = i == 2 ? 0 : i + 1;
+                const int dx = X[i1] - X[i], dy = Y[i1] - Y[i];
+                const bool topleft = dy < 0 || (dy == 0 && dx > 0);
+                Q.fat.E[i][k] = (int64_t)dx * (int64_t)(256 * py0 - Y[i]) - (int64_t)dy * (int64_t)(256 * px0 - X[i]) -
+                                (topleft ? 0 : 1);
+                Q.fat.dx[i][k] = dx;
+                Q.fat.dy[i][k] = dy;
+            }
+            Q.fat.pa[k] = pl.a; Q.fat.pb[k] = pl.b; Q.fat.pe[k] = pl.e;
+            Q.fat.id[k] = id;
+            Q.fat.box[k] = box;
+            return;
+        }
+    }
+    int Xr[3], Yr[3];
+    double m[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = i == 2 ? 0 : i + 1;
+        const int dx = X[i1] - X[i], dy = Y[i1] - Y[i];
+        Xr[i] = X[i] - 256 * tl.x0;
+        Yr[i] = Y[i] - 256 * tl.y0;
+        m[i] = dy != 0 ? (double)dx / (double)dy : 0.0;
+    }
+    const int k = atomicAdd(&Q.big.n, 1);
+    if (k >= kQCap) {                          // queue full: this thread walks the rows itself
+        raster_rows(keys, tile_w, tl, Xr, Yr, m, pl.a, pl.b, pl.e, id, px0 - tl.x0, px1 - tl.x0, py0 - tl.y0,
+                    py1 - tl.y0, (double)cam.cx, (double)cam.cy, w_far);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { Q.big.X[i][k] = Xr[i]; Q.big.Y[i][k] = Yr[i]; Q.big.m[i][k] = m[i]; }
+    Q.big.pa[k] = pl.a; Q.big.pb[k] = pl.b; Q.big.pe[k] = pl.e;
+    Q.big.id[k] = id;
+    Q.big.box[k] = box;
+    const int b0 = (py0 - tl.y0) / kBand, b1 = (py1 - tl.y0) / kBand;
+    const int j0 = atomicAdd(&Q.big.njobs, b1 - b0 + 1);
+    for (int b = b0; b <= b1; ++b) Q.big.job[j0 + b - b0] = (uint16_t)((k << 4) | b);
 }
 
 __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
@@ -240,8 +359,8 @@ __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
 }
 
 // Whole contract for one mesh triangle: transform, far cull, near clip into
-// at most two sub-triangles (same id), setup and rasterization or queueing.
-__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, BigQueue& q, const Tile& tl,
+// at most two sub-triangles (same id), setup and rasterization.
+__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queues& q, const Tile& tl,
                                                 const CamF& cam, double ifx, double ify, float w_far,
                                                 const PoseF& P, const float* __restrict__ xyz,
                                                 const int32_t* __restrict__ tri, const float* __restrict__ nrm,
@@ -258,23 +377,31 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, BigQ
     if (nin == 0) return;
     const WPlane pl = depth_plane(P, nrm + 3 * t, x0, y0, z0, ifx, ify);
     const uint32_t id = (uint32_t)t;
-    if (nin == 3) {
-        emit_tri(keys, tile_w, q, tl, cam, V0, V1, V2, pl, w_far, id);
-    } else if (nin == 2) {
+    // near-plane clip into at most two sub-triangles; one emit call site keeps
+    // a single copy of the setup and rasterization code
+    float3 A0 = V0, B0 = V1, C0 = V2, A1 = V0, B1 = V1, C1 = V2;
+    int nsub = 1;
+    if (nin == 2) {
         const int k = !in0 ? 0 : (!in1 ? 1 : 2);          // the outside vertex
         const float3 O = sel3(k, V0, V1, V2);
         const float3 a = sel3(k == 2 ? 0 : k + 1, V0, V1, V2);
         const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
         const float3 Pb = clip_point(b, O, cam.zn);
         const float3 Pa = clip_point(a, O, cam.zn);
-        emit_tri(keys, tile_w, q, tl, cam, a, b, Pb, pl, w_far, id);
-        emit_tri(keys, tile_w, q, tl, cam, a, Pb, Pa, pl, w_far, id);
-    } else {
+        A0 = a; B0 = b; C0 = Pb;
+        A1 = a; B1 = Pb; C1 = Pa;
+        nsub = 2;
+    } else if (nin == 1) {
         const int k = in0 ? 0 : (in1 ? 1 : 2);            // the inside vertex
         const float3 I = sel3(k, V0, V1, V2);
         const float3 a = sel3(k == 2 ? 0 : k + 1, V0, V1, V2);
         const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
-        emit_tri(keys, tile_w, q, tl, cam, I, clip_point(I, a, cam.zn), clip_point(I, b, cam.zn), pl, w_far, id);
+        A0 = I; B0 = clip_point(I, a, cam.zn); C0 = clip_point(I, b, cam.zn);
+    }
+#pragma unroll 1
+    for (int sub = 0; sub < nsub; ++sub) {
+        const float3 A = sub ? A1 : A0, B = sub ? B1 : B0, C = sub ? C1 : C0;
+        emit_tri(keys, tile_w, q, tl, cam, A, B, C, pl, w_far, id);
     }
 }
 
@@ -364,88 +491,117 @@ __device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
     return s;
 }
 
-// One workgroup per (pose, visible cluster): each thread bins its triangle
-// into the (pose, tile) bins its footprint touches.  Tile counts are
-// aggregated in LDS over the cluster's tile rectangle, then reserved with
-// one global atomic per (workgroup, tile).
+// Workgroups loop over (pose, visible cluster) items; each thread bins its
+// triangle into the (pose, tile) bins its footprint touches.  Tile counts of
+// the two size classes are aggregated in LDS over the cluster's tile
+// rectangle, then reserved with one global atomic per (workgroup, tile,
+// class).  Small footprints fill a bin from the front, large ones from the
+// back, so that the tile pass sees triangles of similar cost together.
+constexpr float kBigFootprint = 144.0f;    // margin-widened bounding box area, px
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
-    __shared__ uint32_t tcnt[kMaxTiles];
-    __shared__ uint32_t tbase[kMaxTiles];
+    __shared__ uint32_t tcnt[kMaxTiles];       // small count | large count << 16, then cursors
+    __shared__ uint32_t tbs[kMaxTiles], tbb[kMaxTiles];
     const int pose = blockIdx.y;
-    const int k = blockIdx.x;
-    if (k >= a.vis_count[pose]) return;
+    const int nvis = a.vis_count[pose];
     const ScanDesc& sd = bd.s[pose_scan(bd, pose)];
     const CamF cam{sd.fx, sd.fy, sd.cx, sd.cy, sd.z_near, sd.z_far, sd.width, sd.height};
-    const uint2 e = a.vis[(int64_t)pose * a.n_clusters + k];
-    const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
-    const int rw = rx1 - rx0 + 1, nrect = rw * (ry1 - ry0 + 1);
-    for (int i = threadIdx.x; i < nrect; i += kWG) tcnt[i] = 0;
     PoseF P;
     load_pose(a.T_wc + 12 * (int64_t)pose, P);
-    const int64_t t = (int64_t)e.x * kClusterTris + threadIdx.x;
-    Foot f;
-    bool ok = false;
-    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
-    float area2 = 0.0f;
-    if (t < a.n_tris) {
-        const uint32_t i0 = min((uint32_t)a.tri[3 * t], a.vmax), i1 = min((uint32_t)a.tri[3 * t + 1], a.vmax),
-                       i2 = min((uint32_t)a.tri[3 * t + 2], a.vmax);
-        const float3 W0 = make_float3(a.xyz[3 * (int64_t)i0], a.xyz[3 * (int64_t)i0 + 1], a.xyz[3 * (int64_t)i0 + 2]);
-        const float3 W1 = make_float3(a.xyz[3 * (int64_t)i1], a.xyz[3 * (int64_t)i1 + 1], a.xyz[3 * (int64_t)i1 + 2]);
-        const float3 W2 = make_float3(a.xyz[3 * (int64_t)i2], a.xyz[3 * (int64_t)i2 + 1], a.xyz[3 * (int64_t)i2 + 2]);
-        ok = footprint(P, cam, W0, W1, W2, f);
-        if (ok) {
-            float umin = f.u[0], umax = f.u[0], vmin = f.v[0], vmax = f.v[0];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int j = (i + 1) & 3;
-                umin = fminf(umin, f.u[i]); umax = fmaxf(umax, f.u[i]);
-                vmin = fminf(vmin, f.v[i]); vmax = fmaxf(vmax, f.v[i]);
-                area2 += f.u[i] * f.v[j] - f.u[j] * f.v[i];
-            }
-            umin -= 2.0f; vmin -= 2.0f; umax += 2.0f; vmax += 2.0f;
-            const float W1f = (float)(cam.W - 1), H1f = (float)(cam.H - 1);
-            ok = umax >= 0.0f && vmax >= 0.0f && umin <= W1f && vmin <= H1f;
-            if (ok) {
-                tx0 = max((int)fmaxf(umin, 0.0f) / TW, rx0);
-                tx1 = min((int)fminf(umax, W1f) / TW, rx1);
-                ty0 = max((int)fmaxf(vmin, 0.0f) / TH, ry0);
-                ty1 = min((int)fminf(vmax, H1f) / TH, ry1);
-            }
-        }
-    }
-    const bool test_tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > 2 && fabsf(area2) > 1e-3f;
-    __syncthreads();
-    if (ok)
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx)
-                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
-                                             (float)(ty * TH + TH - 1)))
-                    atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], 1u);
-    __syncthreads();
     const int pl = pose - sd.pose_off;
     const int ntile = sd.tiles_x * sd.tiles_y;
     const int64_t rec0 = sd.rec_off + (int64_t)pl * ntile;
-    for (int i = threadIdx.x; i < nrect; i += kWG) {
-        const uint32_t n = tcnt[i];
-        if (n) {
-            const int tile = (ry0 + i / rw) * sd.tiles_x + rx0 + i % rw;
-            tbase[i] = (uint32_t)atomicAdd(a.bin_count + rec0 + tile, (int)n);
-            tcnt[i] = 0;
+    const uint32_t cap = (uint32_t)a.bin_cap;
+    for (int k = blockIdx.x; k < nvis; k += gridDim.x) {
+        const uint2 e = a.vis[(int64_t)pose * a.n_clusters + k];
+        const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
+        const int rw = rx1 - rx0 + 1, nrect = rw * (ry1 - ry0 + 1);
+        __syncthreads();                       // previous item's tables are no longer read
+        for (int i = threadIdx.x; i < nrect; i += kWG) tcnt[i] = 0;
+        const int64_t t = (int64_t)e.x * kClusterTris + threadIdx.x;
+        Foot f;
+        bool ok = false, big = false;
+        int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+        float area2 = 0.0f;
+        if (t < a.n_tris) {
+            const uint32_t i0 = min((uint32_t)a.tri[3 * t], a.vmax), i1 = min((uint32_t)a.tri[3 * t + 1], a.vmax),
+                           i2 = min((uint32_t)a.tri[3 * t + 2], a.vmax);
+            const float3 W0 = make_float3(a.xyz[3 * (int64_t)i0], a.xyz[3 * (int64_t)i0 + 1], a.xyz[3 * (int64_t)i0 + 2]);
+            const float3 W1 = make_float3(a.xyz[3 * (int64_t)i1], a.xyz[3 * (int64_t)i1 + 1], a.xyz[3 * (int64_t)i1 + 2]);
+            const float3 W2 = make_float3(a.xyz[3 * (int64_t)i2], a.xyz[3 * (int64_t)i2 + 1], a.xyz[3 * (int64_t)i2 + 2]);
+            ok = footprint(P, cam, W0, W1, W2, f);
+            if (ok) {
+                float umin = f.u[0], umax = f.u[0], vmin = f.v[0], vmax = f.v[0];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = (i + 1) & 3;
+                    umin = fminf(umin, f.u[i]); umax = fmaxf(umax, f.u[i]);
+                    vmin = fminf(vmin, f.v[i]); vmax = fmaxf(vmax, f.v[i]);
+                    area2 += f.u[i] * f.v[j] - f.u[j] * f.v[i];
+                }
+                umin -= 2.0f; vmin -= 2.0f; umax += 2.0f; vmax += 2.0f;
+                big = (umax - umin) * (vmax - vmin) > kBigFootprint;
+                const float W1f = (float)(cam.W - 1), H1f = (float)(cam.H - 1);
+                ok = umax >= 0.0f && vmax >= 0.0f && umin <= W1f && vmin <= H1f;
+                if (ok) {
+                    tx0 = max((int)fmaxf(umin, 0.0f) / TW, rx0);
+                    tx1 = min((int)fminf(umax, W1f) / TW, rx1);
+                    ty0 = max((int)fmaxf(vmin, 0.0f) / TH, ry0);
+                    ty1 = min((int)fminf(vmax, H1f) / TH, ry1);
+                }
+            }
+        }
+        // tiles the footprint touches, as a bit mask over its tile rectangle when it fits in 64 bits
+        const int sw = tx1 - tx0 + 1, nspan = ok ? sw * (ty1 - ty0 + 1) : 0;
+        const bool test_tiles = nspan > 2 && fabsf(area2) > 1e-3f;
+        uint64_t hits = 0;
+        if (nspan <= 64) {
+            for (int i = 0; i < nspan; ++i) {
+                const int tx = tx0 + i % sw, ty = ty0 + i / sw;
+                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
+                                             (float)(ty * TH + TH - 1)))
+                    hits |= 1ull << i;
+            }
+        }
+        const uint32_t inc = big ? 0x10000u : 1u;
+        __syncthreads();
+        for (int i = 0; i < nspan; ++i) {
+            const int tx = tx0 + i % sw, ty = ty0 + i / sw;
+            const bool h = nspan <= 64 ? ((hits >> i) & 1) != 0
+                                       : (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1),
+                                                                   (float)(ty * TH), (float)(ty * TH + TH - 1)));
+            if (h) atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], inc);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nrect; i += kWG) {
+            const uint32_t n = tcnt[i];
+            if (n) {
+                const int tile = (ry0 + i / rw) * sd.tiles_x + rx0 + i % rw;
+                if (n & 0xffffu) tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
+                if (n >> 16) tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
+                tcnt[i] = 0;
+            }
+        }
+        __syncthreads();
+        for (int i = 0; i < nspan; ++i) {
+            const int tx = tx0 + i % sw, ty = ty0 + i / sw;
+            const bool h = nspan <= 64 ? ((hits >> i) & 1) != 0
+                                       : (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1),
+                                                                   (float)(ty * TH), (float)(ty * TH + TH - 1)));
+            if (!h) continue;
+            const int li = (ty - ry0) * rw + (tx - rx0);
+            const uint32_t old = atomicAdd(&tcnt[li], inc);
+            uint32_t* bin = a.bins + (rec0 + ty * sd.tiles_x + tx) * (int64_t)cap;
+            if (big) {
+                const uint32_t slot = tbb[li] + (old >> 16);
+                if (slot < cap) bin[cap - 1 - slot] = (uint32_t)t;
+            } else {
+                const uint32_t slot = tbs[li] + (old & 0xffffu);
+                if (slot < cap) bin[slot] = (uint32_t)t;
+            }
         }
     }
-    __syncthreads();
-    if (ok)
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx)
-                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
-                                             (float)(ty * TH + TH - 1))) {
-                    const int i = (ty - ry0) * rw + (tx - rx0);
-                    const uint32_t slot = tbase[i] + atomicAdd(&tcnt[i], 1u);
-                    if (slot < (uint32_t)a.bin_cap)
-                        a.bins[(rec0 + ty * sd.tiles_x + tx) * (int64_t)a.bin_cap + slot] = (uint32_t)t;
-                }
 }
 
 // ------------------------------------------------------------------ per-pixel comparison
@@ -504,9 +660,7 @@ __device__ __forceinline__ bool decode_item(const BatchDesc& bd, ItemInfo& it) {
 template <int TW, int TH, int MODE>
 __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
     __shared__ uint64_t keys[TW * TH];
-    __shared__ BigQueue q;
-    __shared__ uint32_t clist[kWG];
-    __shared__ int ccount;
+    __shared__ Queues q;
     __shared__ float red[kWG / 64][kRecFields];
 
     ItemInfo it;
@@ -514,7 +668,7 @@ __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
     const ScanDesc& sd = bd.s[it.scan];
     CamF cam{sd.fx, sd.fy, sd.cx, sd.cy, sd.z_near, sd.z_far, sd.width, sd.height};
     const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
-    const double difx = 1.0 / (double)cam.fx, dify = 1.0 / (double)cam.fy;
+    const double difx = (double)ifx, dify = (double)ify;
     const double dcx = (double)cam.cx, dcy = (double)cam.cy;
     const float w_far = 1.0f / cam.zf;
     const int tx = it.tile % sd.tiles_x, ty = it.tile / sd.tiles_x;
@@ -527,56 +681,33 @@ __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
 
     PoseF P;
     load_pose(a.T_wc + 12 * (int64_t)it.pose, P);
-    const int nbin = a.bin_count[it.rec];
-    if (tid == 0) atomicMax(a.bin_max, nbin);
+    const int ns = a.bin_small[it.rec], nb = a.bin_big[it.rec];
+    if (tid == 0) atomicMax(a.bin_max, ns + nb);
 
-    if (nbin <= a.bin_cap) {
-        // the (pose, tile) bin: every triangle whose footprint touches the tile
-        const uint32_t* bin = a.bins + it.rec * (int64_t)a.bin_cap;
-        for (int base = 0; base < nbin; base += kWG) {
-            if (tid == 0) q.n = 0;
-            __syncthreads();
-            if (base + tid < nbin)
-                raster_triangle(keys, TW, q, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax,
-                                (int64_t)bin[base + tid]);
-            __syncthreads();
-            raster_big<TW, TH>(keys, q, tl, dcx, dcy, w_far);
-            __syncthreads();
+    // Rounds of kWG triangles: from the (pose, tile) bin (small footprints at
+    // the front, large at the back), or, if the bin overflowed its capacity,
+    // every triangle of every visible cluster of the pose (slower, same result).
+    const bool use_bin = ns + nb <= a.bin_cap;
+    const int nvis = a.vis_count[it.pose];
+    const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
+    const uint32_t* bin = a.bins + it.rec * (int64_t)a.bin_cap;
+    const int nr = use_bin ? (ns + nb + kWG - 1) / kWG : nvis;
+    for (int r = 0; r < nr; ++r) {
+        if (tid == 0) { q.big.n = 0; q.big.njobs = 0; q.fat.n = 0; }
+        __syncthreads();
+        int64_t t = -1;
+        if (use_bin) {
+            const int i = r * kWG + tid;
+            if (i < ns + nb) t = i < ns ? bin[i] : bin[a.bin_cap - 1 - (i - ns)];
+        } else {
+            t = (int64_t)vis[r].x * kClusterTris + tid;
+            if (t >= a.n_tris) t = -1;
         }
-    } else {
-        // bin overflow: every triangle of every visible cluster whose tile
-        // rectangle holds this tile (slower, same result)
-        const int nvis = a.vis_count[it.pose];
-        const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
-        for (int base = 0; base < nvis; base += kWG) {
-            if (tid == 0) ccount = 0;
-            __syncthreads();
-            bool take = false;
-            uint32_t cid = 0;
-            if (base + tid < nvis) {
-                const uint2 e = vis[base + tid];
-                const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
-                take = tx >= rx0 && tx <= rx1 && ty >= ry0 && ty <= ry1;
-                cid = e.x;
-            }
-            const uint64_t m = __ballot(take);
-            int wbase = 0;
-            if (lane == 0 && m) wbase = atomicAdd(&ccount, __popcll(m));
-            wbase = __shfl(wbase, 0);
-            if (take) clist[wbase + __popcll(m & ((1ull << lane) - 1ull))] = cid;
-            __syncthreads();
-            const int nc = ccount;
-            for (int k = 0; k < nc; ++k) {
-                if (tid == 0) q.n = 0;
-                __syncthreads();
-                const int64_t t = (int64_t)clist[k] * kClusterTris + tid;
-                if (t < a.n_tris)
-                    raster_triangle(keys, TW, q, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax, t);
-                __syncthreads();
-                raster_big<TW, TH>(keys, q, tl, dcx, dcy, w_far);
-                __syncthreads();
-            }
-        }
+        if (t >= 0) raster_triangle(keys, TW, q, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax, t);
+        __syncthreads();
+        if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, dcx, dcy, w_far);
+        if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, dcx, dcy, w_far);
+        __syncthreads();
     }
 
     // ---------------------------------------------------------------- resolve
@@ -797,10 +928,15 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
 
 // ------------------------------------------------------------------ per-pose reduction
 
-// One wave per pose; lane f sums field f over the pose's tiles in tile order
-// (FP64, integers exactly), so the result does not depend on scheduling.
-__global__ void k_reduce(BatchDesc bd, const float* __restrict__ rec, const int32_t* __restrict__ vis_tris,
-                         float eps, int grad, double* __restrict__ out) {
+// One workgroup per pose: 8 lanes per field sum interleaved tiles (FP64,
+// integers exactly), then the 8 partial sums are added in lane order, so the
+// result does not depend on scheduling.
+constexpr int kRedSplit = 8;
+
+__global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd, const float* __restrict__ rec,
+                                                                   const int32_t* __restrict__ vis_tris, float eps,
+                                                                   int grad, double* __restrict__ out) {
+    __shared__ double part[kRedSplit][kRecFields];
     __shared__ double val[kRecFields];
     const int pose = blockIdx.x;
     int s = 0;
@@ -808,38 +944,43 @@ __global__ void k_reduce(BatchDesc bd, const float* __restrict__ rec, const int3
     const ScanDesc& sd = bd.s[s];
     const int ntile = sd.tiles_x * sd.tiles_y;
     const float* r = rec + (sd.rec_off + (int64_t)(pose - sd.pose_off) * ntile) * kRecFields;
-    const int f = threadIdx.x;
-    if (f < kRecFields) {
-        if (f <= 10) {
-            int64_t acc = 0;
-            for (int t = 0; t < ntile; ++t) acc += __float_as_int(r[(int64_t)t * kRecFields + f]);
-            val[f] = (double)acc;
-        } else {
-            double acc = 0.0;
-            for (int t = 0; t < ntile; ++t) acc += (double)r[(int64_t)t * kRecFields + f];
-            val[f] = acc;
-        }
+    const int f = threadIdx.x % kRecFields, j = threadIdx.x / kRecFields;
+    if (f <= 10) {
+        int64_t acc = 0;
+        for (int t = j; t < ntile; t += kRedSplit) acc += __float_as_int(r[(int64_t)t * kRecFields + f]);
+        part[j][f] = (double)acc;
+    } else {
+        double acc = 0.0;
+        for (int t = j; t < ntile; t += kRedSplit) acc += (double)r[(int64_t)t * kRecFields + f];
+        part[j][f] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRecFields) {
+        double x = 0.0;
+        for (int k = 0; k < kRedSplit; ++k) x += part[k][threadIdx.x];
+        val[threadIdx.x] = x;
     }
     __syncthreads();
     double* o = out + (int64_t)pose * RM_OUT_STRIDE;
-    if (f < RM_OUT_STRIDE) {
+    const int g = threadIdx.x;
+    if (g < RM_OUT_STRIDE) {
         double x = 0.0;
-        if (f == RM_OUT_E_TABLE) x = val[0];
-        else if (f == RM_OUT_E_SOFT) x = val[11];
-        else if (f >= RM_OUT_COUNTS && f < RM_OUT_COUNTS + 9) x = val[1 + f - RM_OUT_COUNTS];
-        else if (f == RM_OUT_N_ACTIVE) x = grad ? val[10] : 0.0;
-        else if (f >= RM_OUT_GRAD && f < RM_OUT_GRAD + 6)
-            x = grad ? (4.0 / ((double)eps * (double)eps)) * val[12 + f - RM_OUT_GRAD] : 0.0;
-        else if (f >= RM_OUT_JTR && f < RM_OUT_JTR + 6) x = grad ? val[12 + f - RM_OUT_JTR] : 0.0;
-        else if (f >= RM_OUT_JTJ && f < RM_OUT_JTJ + 21) x = grad ? val[18 + f - RM_OUT_JTJ] : 0.0;
-        else if (f == RM_OUT_N_VISIBLE) x = (double)vis_tris[pose];
-        o[f] = x;
+        if (g == RM_OUT_E_TABLE) x = val[0];
+        else if (g == RM_OUT_E_SOFT) x = val[11];
+        else if (g >= RM_OUT_COUNTS && g < RM_OUT_COUNTS + 9) x = val[1 + g - RM_OUT_COUNTS];
+        else if (g == RM_OUT_N_ACTIVE) x = grad ? val[10] : 0.0;
+        else if (g >= RM_OUT_GRAD && g < RM_OUT_GRAD + 6)
+            x = grad ? (4.0 / ((double)eps * (double)eps)) * val[12 + g - RM_OUT_GRAD] : 0.0;
+        else if (g >= RM_OUT_JTR && g < RM_OUT_JTR + 6) x = grad ? val[12 + g - RM_OUT_JTR] : 0.0;
+        else if (g >= RM_OUT_JTJ && g < RM_OUT_JTJ + 21) x = grad ? val[18 + g - RM_OUT_JTJ] : 0.0;
+        else if (g == RM_OUT_N_VISIBLE) x = (double)vis_tris[pose];
+        o[g] = x;
     }
 }
 
 template <int TW, int TH>
 hipError_t launch_bin_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
-    const dim3 grid((unsigned)(a.n_clusters > 0 ? a.n_clusters : 1), (unsigned)bd.n_poses);
+    const dim3 grid((unsigned)std::min(a.n_clusters > 0 ? a.n_clusters : 1, 256), (unsigned)bd.n_poses);
     hipLaunchKernelGGL((k_bin<TW, TH>), grid, dim3(kWG), 0, st, bd, a);
     return hipGetLastError();
 }
@@ -881,7 +1022,8 @@ hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& 
 hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec, const int32_t* vis_tris,
                          float eps, int grad, double* out) {
     if (bd.n_poses == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)bd.n_poses), dim3(64), 0, st, bd, rec, vis_tris, eps, grad, out);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)bd.n_poses), dim3(kRecFields * kRedSplit), 0, st, bd, rec, vis_tris,
+                       eps, grad, out);
     return hipGetLastError();
 }
 
