@@ -263,6 +263,14 @@ int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, i
  * [P][6] f64, nullable. */
 int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda,
                double* T_wc, double* delta_out);
+/* Adam step on the se(3) increment from the GRAD field of the result
+ * records (first and second moments m, v: device [P][6] f64, updated in
+ * place; step = 1 for the first call):
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   delta = -lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + 1e-12),
+ *   T_wc <- T_wc exp(delta). */
+int rm_adam_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lr, double beta1, double beta2,
+                 int32_t step, double* m, double* v, double* T_wc);
 /* T_out = T_in exp(delta) for P poses (device [P][12], [P][6], [P][12] f64;
  * T_out may equal T_in). */
 int rm_se3_retract(rm_ctx* ctx, const double* T_in, const double* delta, int32_t n_poses,

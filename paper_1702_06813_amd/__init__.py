@@ -6,5 +6,5 @@ C ABI (include/rendermap.h).  PyTorch provides device memory and streams.
 from .rendermap import (  # noqa: F401
     ABI_SYMBOLS, FO, FU, NONE, OUT_COUNTS, OUT_E_SOFT, OUT_E_TABLE, OUT_GRAD, OUT_JTJ, OUT_JTR, OUT_N_ACTIVE,
     OUT_N_VISIBLE, OUT_STRIDE, UO, AlignCost, Context, Graph, Mesh, RenderMapError, Scan, align_cost,
-    align_cost_grad, context, gn_step, load_library, mesh_from_range, render_depth, scan_image, se3_retract,
+    adam_step, align_cost_grad, context, gn_step, load_library, mesh_from_range, render_depth, scan_image, se3_retract,
 )

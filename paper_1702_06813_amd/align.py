@@ -1,0 +1,215 @@
+"""Pose alignment drivers over the library's batched scoring.
+
+batched_align  -- many independent alignments at once: every iteration is one
+                  rm_align_cost_grad launch over all poses followed by the
+                  on-device pose update (Levenberg-Marquardt or Adam), with
+                  the inlier threshold eps annealed geometrically; the whole
+                  iteration sequence can be captured once as a hipGraph and
+                  replayed.
+plain_align    -- the paper's optimizer for its own cost (Sec. IV-C): a
+                  derivative-free hybrid of an initial gradient descent (finite
+                  differences), Nelder-Mead iterations and coordinate descent
+                  near the minimum, minimizing E(X) of Table I with one render
+                  (one rm_align_cost launch for a single pose) per evaluation.
+
+Pose increments x = (upsilon, omega) are applied on the right, T exp(x).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rendermap as R
+
+
+def eps_schedule(iters: int, eps0: float = 0.5, eps1: float = 0.1):
+    """Geometric annealing of the inlier threshold from eps0 to eps1.  At
+    10 cm / 5 deg most residuals exceed the paper's 0.1 m and carry no
+    gradient; a wide threshold first, then the paper's value, keeps the
+    basin wide and ends on the paper's cost."""
+    if iters <= 1:
+        return [eps1]
+    return [float(eps0 * (eps1 / eps0) ** (k / (iters - 1))) for k in range(iters)]
+
+
+class BatchedAligner:
+    """Fixed-shape batched alignment (mesh, scans and pose count fixed), with
+    optional hipGraph capture of the full iteration sequence."""
+
+    def __init__(self, mesh, scans, n_poses, iters=20, eps=(0.5, 0.1), method="gn", lam=1e-3, lr=0.01,
+                 poses_per_scan=None, device=None):
+        self.mesh, self.scans = mesh, scans
+        self.dev = mesh.xyz.device if device is None else device
+        self.iters, self.method, self.lam, self.lr = iters, method, lam, lr
+        self.eps = eps_schedule(iters, *eps)
+        self.pps = poses_per_scan
+        self.T = torch.empty((n_poses, 12), dtype=torch.float64, device=self.dev)
+        self.out = torch.empty((n_poses, R.OUT_STRIDE), dtype=torch.float64, device=self.dev)
+        self.m = torch.zeros((n_poses, 6), dtype=torch.float64, device=self.dev)
+        self.v = torch.zeros((n_poses, 6), dtype=torch.float64, device=self.dev)
+        self.graph = None
+
+    def _iterations(self):
+        for k, e in enumerate(self.eps):
+            R.align_cost_grad(self.mesh, self.scans, self.T, e, poses_per_scan=self.pps, out=self.out)
+            if self.method == "gn":
+                R.gn_step(self.out, self.T, self.lam)
+            else:
+                R.adam_step(self.out, self.T, self.m, self.v, k + 1, self.lr)
+
+    def run(self, T0: torch.Tensor, use_graph=False):
+        """Aligns every pose of T0 ([P,12] f64 on the device); returns T (in place buffer)."""
+        self.T.copy_(T0.reshape(-1, 12))
+        self.m.zero_()
+        self.v.zero_()
+        if not use_graph:
+            self._iterations()
+            return self.T
+        if self.graph is None:
+            self._iterations()                   # sizes scratch; then reset and capture
+            torch.cuda.synchronize(self.dev)
+            self.T.copy_(T0.reshape(-1, 12))
+            self.m.zero_()
+            self.v.zero_()
+            torch.cuda.synchronize(self.dev)
+            g = R.Graph(self.dev)
+            with g:
+                self._iterations()
+            self.graph = g
+            self.T.copy_(T0.reshape(-1, 12))
+            self.m.zero_()
+            self.v.zero_()
+        self.graph.replay()
+        return self.T
+
+
+def batched_align(mesh, scans, T0, iters=20, eps=(0.5, 0.1), method="gn", lam=1e-3, lr=0.01, poses_per_scan=None):
+    a = BatchedAligner(mesh, scans, T0.reshape(-1, 12).shape[0], iters, eps, method, lam, lr, poses_per_scan)
+    return a.run(T0).clone()
+
+
+# ---------------------------------------------------------------------------- derivative-free (the paper's)
+
+def nelder_mead(f, x0, scale, max_evals, tol=1e-9):
+    """Standard Nelder-Mead (reflection 1, expansion 2, contraction 1/2,
+    shrink 1/2) from the simplex x0 + scale_i e_i.  Returns (x, fx, evals)."""
+    n = len(x0)
+    pts = [np.array(x0, float)] + [np.array(x0, float) + scale[i] * np.eye(n)[i] for i in range(n)]
+    vals = [f(p) for p in pts]
+    evals = n + 1
+    while evals < max_evals:
+        order = np.argsort(vals)
+        pts = [pts[i] for i in order]
+        vals = [vals[i] for i in order]
+        if abs(vals[-1] - vals[0]) <= tol and np.max(np.abs(np.array(pts[1:]) - pts[0])) <= tol:
+            break
+        c = np.mean(pts[:-1], axis=0)
+        xr = c + (c - pts[-1])
+        fr = f(xr); evals += 1
+        if fr < vals[0]:
+            xe = c + 2.0 * (c - pts[-1])
+            fe = f(xe); evals += 1
+            if fe < fr:
+                pts[-1], vals[-1] = xe, fe
+            else:
+                pts[-1], vals[-1] = xr, fr
+        elif fr < vals[-2]:
+            pts[-1], vals[-1] = xr, fr
+        else:
+            xc = c + 0.5 * (pts[-1] - c) if fr >= vals[-1] else c + 0.5 * (xr - c)
+            fc = f(xc); evals += 1
+            if fc < min(fr, vals[-1]):
+                pts[-1], vals[-1] = xc, fc
+            else:
+                for i in range(1, len(pts)):
+                    pts[i] = pts[0] + 0.5 * (pts[i] - pts[0])
+                    vals[i] = f(pts[i]); evals += 1
+    i = int(np.argmin(vals))
+    return pts[i], vals[i], evals
+
+
+def coordinate_descent(f, x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
+    """Coordinate descent with per-axis step halving near the minimum."""
+    x, fx, evals = np.array(x0, float), f0, 0
+    step = np.array(step, float)
+    while evals < max_evals and np.any(step > min_step):
+        improved = False
+        for i in range(len(x)):
+            if step[i] <= min_step:
+                continue
+            for s in (+1.0, -1.0):
+                y = x.copy(); y[i] += s * step[i]
+                fy = f(y); evals += 1
+                if fy < fx:
+                    x, fx, improved = y, fy, True
+                    break
+            else:
+                step[i] *= shrink
+            if evals >= max_evals:
+                break
+    return x, fx, evals
+
+
+def hybrid_minimize(f, n=6, budget=700, fd_step=(0.02, 0.02, 0.02, 0.02, 0.02, 0.02),
+                    simplex=(0.05, 0.05, 0.05, 0.05, 0.05, 0.05), gd_iters=2, nm_share=0.6):
+    """Initial gradient descent by central differences with a backtracking
+    line search, then Nelder-Mead, then coordinate descent (Sec. IV-C).
+    Returns (x, fx, evals)."""
+    x = np.zeros(n)
+    fx = f(x)
+    evals = 1
+    h = np.asarray(fd_step, float)
+    for _ in range(gd_iters):
+        g = np.zeros(n)
+        for i in range(n):
+            e = np.zeros(n); e[i] = h[i]
+            g[i] = (f(x + e) - f(x - e)) / (2 * h[i])
+            evals += 2
+        gn = np.linalg.norm(g / h)
+        if gn == 0:
+            break
+        d = -(g / h) / gn * h * 4.0           # a few finite-difference steps along -grad
+        t = 1.0
+        for _ in range(6):
+            y = x + t * d
+            fy = f(y); evals += 1
+            if fy < fx:
+                x, fx = y, fy
+                break
+            t *= 0.5
+    x, fx, e1 = nelder_mead(f, x, np.asarray(simplex, float), int((budget - evals) * nm_share) + evals)
+    evals += e1
+    x2, fx2, e2 = coordinate_descent(f, x, fx, np.asarray(simplex, float) * 0.25, budget - evals)
+    return (x2, fx2, evals + e2) if fx2 <= fx else (x, fx, evals + e2)
+
+
+def plain_align(mesh, scan, T0, eps=0.1, budget=700):
+    """The paper's plain form: minimize E(X) (Table I) of one pose with the
+    derivative-free hybrid optimizer, one single-pose render per evaluation.
+    T0: [12] or [3,4] (host).  Returns (T [3,4] numpy, E, evaluations)."""
+    dev = mesh.xyz.device
+    T0d = torch.as_tensor(np.asarray(T0, np.float64).reshape(1, 12), device=dev)
+    xd = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+    Td = torch.empty_like(T0d)
+    out = torch.empty((1, R.OUT_STRIDE), dtype=torch.float64, device=dev)
+
+    def f(x):
+        xd.copy_(torch.from_numpy(np.asarray(x, np.float64).reshape(1, 6)))
+        R.se3_retract(T0d, xd, out=Td)
+        R.align_cost(mesh, scan, Td, eps, out=out)
+        return float(out[0, R.OUT_E_TABLE].item())
+
+    x, fx, evals = hybrid_minimize(f, budget=budget)
+    xd.copy_(torch.from_numpy(np.asarray(x, np.float64).reshape(1, 6)))
+    R.se3_retract(T0d, xd, out=Td)
+    return Td.cpu().numpy().reshape(3, 4), fx, evals
+
+
+def pose_errors(T, T_true):
+    """Translation error (m) and rotation angle error (rad) of each pose."""
+    T = np.asarray(T, np.float64).reshape(-1, 3, 4)
+    Tt = np.asarray(T_true, np.float64).reshape(3, 4)
+    dt = np.linalg.norm(T[:, :, 3] - Tt[:, 3], axis=1)
+    Rrel = np.einsum("kji,jl->kil", T[:, :, :3], Tt[:, :3])
+    ang = np.arccos(np.clip((np.trace(Rrel, axis1=1, axis2=2) - 1) / 2, -1, 1))
+    return dt, ang

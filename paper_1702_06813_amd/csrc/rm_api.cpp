@@ -600,6 +600,20 @@ int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda, d
     return RM_OK;
 }
 
+int rm_adam_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lr, double beta1, double beta2, int32_t step,
+                 double* m, double* v, double* T_wc) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (n_poses < 0) return fail(ctx, RM_ERR_INVALID_ARG, "n_poses < 0");
+    if (n_poses == 0) return RM_OK;
+    if (!out || !m || !v || !T_wc) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || step < 1)
+        return fail(ctx, RM_ERR_INVALID_ARG, "need lr > 0, 0 <= beta < 1, step >= 1");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_adam_step(ctx->stream, out, n_poses, lr, beta1, beta2, step, m, v, T_wc));
+    return RM_OK;
+}
+
 int rm_se3_retract(rm_ctx* ctx, const double* T_in, const double* delta, int32_t n_poses, double* T_out) {
     if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
     ctx->err.clear();

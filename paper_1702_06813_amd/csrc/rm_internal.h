@@ -95,6 +95,8 @@ hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec,
                          const int32_t* vis_tris, float eps, int grad, double* out);
 hipError_t launch_gn_step(hipStream_t st, const double* out, int32_t P, double lambda, double* T,
                           double* delta_out);
+hipError_t launch_adam_step(hipStream_t st, const double* out, int32_t P, double lr, double b1, double b2,
+                            int32_t step, double* m, double* v, double* T);
 hipError_t launch_retract(hipStream_t st, const double* T_in, const double* delta, int32_t P,
                           double* T_out);
 

@@ -1,5 +1,7 @@
 // Optimizer step on the device: Levenberg-Marquardt increment from the
 // per-pose Gauss-Newton blocks and the SE(3) retraction T <- T exp(delta).
+#include <cmath>
+
 #include "rm_internal.h"
 
 namespace rm {
@@ -105,7 +107,36 @@ __global__ void k_retract(const double* __restrict__ Tin, const double* __restri
     retract(T, d, Tout + 12 * (int64_t)p);
 }
 
+__global__ void k_adam_step(const double* __restrict__ out, int32_t P, double lr, double b1, double b2,
+                            double c1, double c2, double* __restrict__ m, double* __restrict__ v,
+                            double* __restrict__ T) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double d[6];
+    for (int i = 0; i < 6; ++i) {
+        const double g = out[(int64_t)p * RM_OUT_STRIDE + RM_OUT_GRAD + i];
+        const double mi = b1 * m[6 * (int64_t)p + i] + (1.0 - b1) * g;
+        const double vi = b2 * v[6 * (int64_t)p + i] + (1.0 - b2) * g * g;
+        m[6 * (int64_t)p + i] = mi;
+        v[6 * (int64_t)p + i] = vi;
+        d[i] = -lr * (mi / c1) / (sqrt(vi / c2) + 1e-12);
+    }
+    double* Tp = T + 12 * (int64_t)p;
+    double Tin[12];
+    for (int i = 0; i < 12; ++i) Tin[i] = Tp[i];
+    retract(Tin, d, Tp);
+}
+
 }  // namespace
+
+hipError_t launch_adam_step(hipStream_t st, const double* out, int32_t P, double lr, double b1, double b2,
+                            int32_t step, double* m, double* v, double* T) {
+    if (P <= 0) return hipSuccess;
+    const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+    hipLaunchKernelGGL(k_adam_step, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, out, P, lr, b1, b2, c1, c2, m, v,
+                       T);
+    return hipGetLastError();
+}
 
 hipError_t launch_gn_step(hipStream_t st, const double* out, int32_t P, double lambda, double* T,
                           double* delta_out) {

@@ -28,7 +28,7 @@ ABI_SYMBOLS = [
     "rm_ctx_create", "rm_ctx_destroy", "rm_ctx_set_stream", "rm_last_error", "rm_set_tile", "rm_autotune",
     "rm_get_tile", "rm_profile", "rm_profile_read", "rm_graph_begin", "rm_graph_end", "rm_graph_launch", "rm_graph_destroy", "rm_scan_image",
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
-    "rm_align_cost_grad", "rm_gn_step", "rm_se3_retract",
+    "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract",
 ]
 
 
@@ -93,6 +93,7 @@ def load_library(path: Path | str | None = None):
             "rm_align_cost": [V, ctypes.POINTER(CMesh), ctypes.POINTER(CScan), I32, V, V, CCostParams, V],
             "rm_align_cost_grad": [V, ctypes.POINTER(CMesh), ctypes.POINTER(CScan), I32, V, V, CCostParams, V],
             "rm_gn_step": [V, V, I32, D, V, V],
+            "rm_adam_step": [V, V, I32, D, D, D, I32, V, V, V],
             "rm_se3_retract": [V, V, V, I32, V],
         }
         for name, args in sig.items():
@@ -381,6 +382,20 @@ def gn_step(out: torch.Tensor, T_wc: torch.Tensor, lam: float = 0.0, delta_out=N
     _need(out, torch.float64, "out", dev)
     P = T.reshape(-1, 12).shape[0]
     context(dev).call("rm_gn_step", _ptr(out), P, float(lam), _ptr(T), _ptr(delta_out))
+    return T_wc
+
+
+def adam_step(out: torch.Tensor, T_wc: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999):
+    """rm_adam_step: Adam on the se(3) increment from the GRAD field; T_wc, m, v in place."""
+    dev = T_wc.device
+    T = _need(T_wc, torch.float64, "T_wc", dev)
+    _need(out, torch.float64, "out", dev)
+    _need(m, torch.float64, "m", dev)
+    _need(v, torch.float64, "v", dev)
+    P = T.reshape(-1, 12).shape[0]
+    context(dev).call("rm_adam_step", _ptr(out), P, float(lr), float(beta1), float(beta2), int(step), _ptr(m),
+                      _ptr(v), _ptr(T))
     return T_wc
 
 

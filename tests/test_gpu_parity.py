@@ -403,3 +403,45 @@ def test_graph_replay_matches_eager(rm):
         np.testing.assert_array_equal(outg.cpu().numpy(), eager[it][0].cpu().numpy())
         np.testing.assert_array_equal(Tg.cpu().numpy(), eager[it][1].cpu().numpy())
         del junk
+
+
+# ------------------------------------------------------------------ alignment drivers
+
+def test_batched_alignment_converges_and_graph_matches(rm):
+    """Gauss-Newton with the eps schedule brings 5 cm / 2 deg starts on the
+    Kinect-like map to centimetre level; replaying the captured graph gives
+    the same poses as eager execution."""
+    _say("batched alignment")
+    from paper_1702_06813_amd import align as A
+    w = workload("kinect")
+    dm = _dev_mesh(rm, oracle_map("kinect"))
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    rng = np.random.default_rng(21)
+    T0 = _T([S.perturb(w.T_true, rng, 0.05, np.deg2rad(2.0), fixed=True) for _ in range(8)])
+    al = A.BatchedAligner(dm, scan, 8, iters=20)
+    Te = al.run(T0).clone().cpu().numpy()
+    Tg = al.run(T0, use_graph=True).clone()
+    Tg2 = al.run(T0, use_graph=True).clone()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(Tg.cpu().numpy(), Te)
+    np.testing.assert_array_equal(Tg2.cpu().numpy(), Te)
+    dt0, da0 = A.pose_errors(T0.cpu().numpy(), w.T_true)
+    dt, da = A.pose_errors(Te, w.T_true)
+    assert np.median(dt) < 0.02 and np.median(dt) < 0.5 * np.median(dt0), (dt, dt0)
+    assert np.median(da) < np.deg2rad(1.0), np.rad2deg(da)
+
+
+def test_plain_form_reduces_table_cost(rm):
+    _say("plain form")
+    from paper_1702_06813_amd import align as A
+    w = workload("kinect")
+    dm = _dev_mesh(rm, oracle_map("kinect"))
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    rng = np.random.default_rng(22)
+    T0 = S.perturb(w.T_true, rng, 0.05, np.deg2rad(2.0), fixed=True)
+    e0 = rm.align_cost(dm, scan, _T([T0]), EPS).cpu().numpy()[0, 0]
+    T, e, ev = A.plain_align(dm, scan, T0, eps=EPS, budget=300)
+    assert ev <= 300 and e < e0
+    dt0, _ = A.pose_errors(T0, w.T_true)
+    dt, _ = A.pose_errors(T, w.T_true)
+    assert dt[0] < dt0[0]

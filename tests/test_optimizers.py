@@ -1,0 +1,48 @@
+"""Host logic of the alignment drivers (CPU): the derivative-free pieces on
+textbook functions, the eps schedule, and the pose error measure."""
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+from paper_1702_06813_amd import align as A
+
+
+def test_nelder_mead_rosenbrock():
+    """Rosenbrock's valley (the paper likens its cost to it): NM reaches (1, 1)."""
+    f = lambda x: (1 - x[0]) ** 2 + 100 * (x[1] - x[0] ** 2) ** 2
+    x, fx, ev = A.nelder_mead(f, np.array([-1.2, 1.0]), np.array([0.5, 0.5]), 2000, tol=1e-14)
+    assert np.allclose(x, [1, 1], atol=1e-4) and fx < 1e-8
+
+
+def test_coordinate_descent_separable_quadratic():
+    c = np.array([0.3, -0.2, 0.05, 0.1, -0.4, 0.25])
+    f = lambda x: float(np.sum((x - c) ** 2))
+    x, fx, ev = A.coordinate_descent(f, np.zeros(6), f(np.zeros(6)), np.full(6, 0.1), 5000, min_step=1e-6)
+    assert np.allclose(x, c, atol=1e-5)
+
+
+def test_hybrid_on_quantized_cost_within_budget():
+    """A piecewise-constant cost (integer counts, like Table I's E): the
+    hybrid optimizer gets within the quantization of the minimum using at
+    most its evaluation budget."""
+    c = np.array([0.04, -0.03, 0.02, 0.03, -0.02, 0.01])
+    calls = []
+    def f(x):
+        calls.append(1)
+        return float(np.floor(2e4 * np.sum((x - c) ** 2)))
+    x, fx, ev = A.hybrid_minimize(f, budget=700)
+    assert ev == len(calls) <= 700
+    assert np.sum((x - c) ** 2) < 3e-4
+
+
+def test_eps_schedule():
+    e = A.eps_schedule(20, 0.5, 0.1)
+    assert len(e) == 20 and abs(e[0] - 0.5) < 1e-12 and abs(e[-1] - 0.1) < 1e-12
+    assert all(a > b for a, b in zip(e, e[1:]))
+    assert A.eps_schedule(1) == [0.1]
+
+
+def test_pose_errors():
+    T = np.zeros((3, 4)); T[:, :3] = np.eye(3)
+    T2 = T.copy(); T2[:, :3] = Rotation.from_rotvec([0, 0, 0.1]).as_matrix(); T2[:, 3] = [0.03, 0.04, 0]
+    dt, ang = A.pose_errors(T2, T)
+    assert abs(dt[0] - 0.05) < 1e-12 and abs(ang[0] - 0.1) < 1e-9
