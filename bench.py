@@ -41,7 +41,8 @@ def build_inputs(rm, torch, dev):
     t0 = time.time()
     w = configs.differentiation()
     log(f"workload generated in {time.time() - t0:.1f}s")
-    parts = [rm.mesh_from_range(torch.from_numpy(d).to(dev), w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge)
+    parts = [rm.mesh_from_range(torch.from_numpy(d).to(dev), w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge,
+                               w.smooth_radius)
              for T, d in zip(w.views, w.view_depths)]
     mesh = rm.Mesh.concat(parts).prepare()
     scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(dev), w.z_min, w.z_max, cam=w.cam)
@@ -59,7 +60,7 @@ def cpu_baseline(w, torch, n_poses=2):
     off = 0
     xyz, tri, cls = [], [], []
     for T, d in zip(w.views, w.view_depths):
-        v, t, c = O.meshify(d, w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge)
+        v, t, c = O.meshify(d, w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge, w.smooth_radius)
         xyz.append(v); tri.append(t + off); cls.append(c); off += len(v)
     mesh_np = (np.concatenate(xyz), np.concatenate(tri).astype(np.int32), np.concatenate(cls))
     d, c = O.scan_image(w.scan_depth, w.z_min, w.z_max)

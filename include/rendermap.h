@@ -99,8 +99,11 @@ typedef struct {
 /* Per-pose result record: RM_OUT_STRIDE doubles per pose.
  *   E_TABLE    E(X) = sum over pixels of the Table I value (+1/-1/0); exact
  *   E_SOFT     sum over pixels of rho_p = 2 min(r_p^2/eps^2, 1) - 1 on scored
- *              cells, 0 elsewhere, with r_p = dz (map FO / scan FO),
- *              min(dz, 0) (FO / FU), max(dz, 0) (FU / FO), dz = d(p_r) - d(p_s)
+ *              cells, 0 elsewhere, with r_p = e_p (map FO / scan FO),
+ *              min(e_p, 0) (FO / FU), max(e_p, 0) (FU / FO); e_p = dz |n . r|
+ *              is the signed distance of the scan point d(p_s) r from the
+ *              plane of the triangle the pixel sees (positive on the camera
+ *              side), dz = d(p_r) - d(p_s) the Table I depth difference
  *   COUNTS     9 pixel counts: FO/FO reward, FO/FO penalty, FO/FU reward,
  *              FO/FU penalty, FU/FO reward, FU/FO penalty, ignored because the
  *              scan pixel is NaN, ignored because the map pixel is NaN or UO,
@@ -112,9 +115,10 @@ typedef struct {
  *              row-major (21 values)
  *   N_VISIBLE  triangles in clusters that survived frustum culling
  * GRAD/JTR/JTJ/N_ACTIVE are written by rm_align_cost_grad only (zero from
- * rm_align_cost).  J_p = [-n ; n x P] / (n . r) is the derivative of the
- * rendered depth at pixel p, n the winning triangle's camera-frame normal,
- * r = ((u - cx)/fx, (v - cy)/fy, 1), P = d(p_r) r. */
+ * rm_align_cost).  J_p = [m ; P_s x m] is the derivative of e_p under
+ * T_wc exp(delta) with the winning triangle held fixed: n is that triangle's
+ * camera-frame unit normal, m = n turned towards the camera (m . r < 0),
+ * r = ((u - cx)/fx, (v - cy)/fy, 1), P_s = d(p_s) r. */
 enum {
     RM_OUT_E_TABLE = 0,
     RM_OUT_E_SOFT = 1,
@@ -194,7 +198,14 @@ int rm_scan_image(rm_ctx* ctx, const float* depth, int32_t height, int32_t width
  * (j*stride, i*stride), i < ceil(H/stride), j < ceil(W/stride); a node is
  * classified as in rm_scan_image, back-projected at its depth (z_max for a
  * no-return) through `cam` and moved to the world by T_wc (host, 12 doubles),
- * in FP64, then rounded to f32.  Vertex i*gw + j belongs to node (i, j)
+ * in FP64, then rounded to f32.  With smooth_radius R > 0 the depth of a
+ * valid node is the FP64 mean of the valid pixels of the (2R+1)^2 window
+ * centred on it (clipped to the image, rows then columns in increasing
+ * order) whose depth differs from the node pixel's by at most RM_SMOOTH_REL
+ * of it: an edge-preserving box filter that reduces range noise before the
+ * surfaces are built (the paper suggests blurring the depth images to lower
+ * the noise of the cost, Sec. IV-C); R = 0 uses the node pixel alone.
+ * Vertex i*gw + j belongs to node (i, j)
  * (gw = ceil(W/stride)); dead nodes get an unreferenced NaN vertex.  The quad
  * between nodes (i,j), (i,j+1), (i+1,j), (i+1,j+1) is dropped if a corner is
  * dead, is RM_FU if a corner is a no-return or one of its four sides is
@@ -204,11 +215,14 @@ int rm_scan_image(rm_ctx* ctx, const float* depth, int32_t height, int32_t width
  *   xyz_out  device [gh*gw][3] f32 (gh = ceil(H/stride))
  *   tri_out  device [cap_t][3] i32,  cls_out device [cap_t] u8
  *   n_v_out, n_t_out  host; receive gh*gw and the triangle count.
+ * smooth_radius must lie in 0..RM_MAX_SMOOTH_RADIUS.
  * Synchronizes the context stream to read the count back.  If more than
  * cap_t triangles result, returns RM_ERR_CAPACITY (n_t_out holds the
  * needed count; the outputs are unspecified). */
+#define RM_SMOOTH_REL 0.03
+#define RM_MAX_SMOOTH_RADIUS 16
 int rm_mesh_from_range(rm_ctx* ctx, const float* depth, rm_camera cam, const double* T_wc,
-                       int32_t stride, float z_min, float z_max, float max_edge,
+                       int32_t stride, int32_t smooth_radius, float z_min, float z_max, float max_edge,
                        float* xyz_out, int32_t* tri_out, uint8_t* cls_out, int64_t cap_t,
                        int64_t* n_v_out, int64_t* n_t_out);
 

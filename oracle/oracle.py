@@ -16,19 +16,26 @@ Pieces, each following the paper:
 E_soft (a project definition; the paper optimizes E derivative-free):
     rho_p = 2 * min(r_p^2 / eps^2, 1) - 1   on the three scored cells,
     rho_p = 0                              on ignored cells, with
-    r_p = dz          (map FO, scan FO)
-    r_p = min(dz, 0)  (map FO, scan FU: penalty side is dz <= 0)
-    r_p = max(dz, 0)  (map FU, scan FO: penalty side is dz > 0)
-    dz  = d(p_r) - d(p_s)  (Table I).
-rho equals Table I's +1 once |r| >= eps and -1 where the Table I cell is a
-reward with r = 0.  A pixel is *active* when its residual moves with the pose:
+    r_p = e_p          (map FO, scan FO)
+    r_p = min(e_p, 0)  (map FO, scan FU: penalty side is dz <= 0)
+    r_p = max(e_p, 0)  (map FU, scan FO: penalty side is dz > 0)
+    e_p = dz * |n^ . ray|,  dz = d(p_r) - d(p_s)  (Table I),
+where n^ is the winning triangle's camera-frame unit normal and
+ray = ((u-cx)/fx, (v-cy)/fy, 1): e_p is the signed distance of the scan point
+P_s = d(p_s) ray from the plane of the triangle the pixel sees, positive when
+the scan point lies on the camera side (the sign of dz).  Measured across the
+plane rather than along the ray, it stays bounded where the ray grazes the
+triangle; Table I itself still decides on dz.
+rho equals -1 where the Table I cell is a reward with r = 0, and +1 once
+|r| >= eps.  A pixel is *active* when its residual moves with the pose:
 scored, r^2 < eps^2, and (FO/FO, or FO/FU with dz < 0, or FU/FO with dz > 0).
     grad E_soft = (4 / eps^2) * sum_active r_p J_p
     H = sum_active J_p^T J_p ,  b = sum_active r_p J_p
-J_p is the derivative of the rendered depth at pixel p with respect to a
-right perturbation T_wc * exp(delta), delta = (upsilon, omega):
-    J_p = [ -n ; n x P ] / (n . r),   P = z r,  r = ((u-cx)/fx, (v-cy)/fy, 1)
-with n the winning triangle's camera-frame plane normal.
+J_p is the derivative of e_p with respect to a right perturbation
+T_wc * exp(delta), delta = (upsilon, omega), the winning triangle held fixed:
+e_p = m_w . (T_wc P_s) - c_w for the world plane m_w . X = c_w, so
+    J_p = [ m ; P_s x m ],   m = n^ oriented towards the camera (m . ray < 0;
+                             m = -n^ when n^ . ray = 0).
 """
 from __future__ import annotations
 
@@ -84,7 +91,7 @@ def lib():
         L.or_num_threads.restype = ctypes.c_int
         L.or_scan_image.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, P, P]
         L.or_meshify.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_Cam), P,
-                                 ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  P, P, P, ctypes.c_int64, P]
         L.or_meshify.restype = ctypes.c_int64
         L.or_render.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.POINTER(_Cam),
@@ -127,7 +134,7 @@ def scan_image(depth, z_min=0.5, z_max=8.0):
     return d, c
 
 
-def meshify(depth, cam, T_wc, stride, z_min=0.5, z_max=8.0, max_edge=0.1):
+def meshify(depth, cam, T_wc, stride, z_min=0.5, z_max=8.0, max_edge=0.1, smooth_radius=0):
     """Interface mesh (xyz f32 [V,3], tri i32 [T,3], cls u8 [T]) of a range image."""
     depth = np.ascontiguousarray(depth, dtype=np.float32)
     H, W = depth.shape
@@ -138,7 +145,7 @@ def meshify(depth, cam, T_wc, stride, z_min=0.5, z_max=8.0, max_edge=0.1):
     cls = np.empty(max(cap_t, 1), np.uint8)
     nv = ctypes.c_int64(0)
     c = _cam(cam)
-    nt = lib().or_meshify(_ptr(depth), H, W, ctypes.byref(c), _ptr(_pose(T_wc)), stride,
+    nt = lib().or_meshify(_ptr(depth), H, W, ctypes.byref(c), _ptr(_pose(T_wc)), stride, smooth_radius,
                           z_min, z_max, max_edge, _ptr(xyz), _ptr(tri), _ptr(cls), cap_t,
                           ctypes.byref(nv))
     assert nt >= 0
@@ -235,13 +242,15 @@ def table1(c_r, c_s, dz, eps):
     return s, cell
 
 
-def residual(c_r, c_s, dz):
-    """E_soft residual r_p, the mask of scored cells and the active mask."""
+def residual(c_r, c_s, dz, g=1.0):
+    """E_soft residual r_p from dz and the plane factor g = |n^ . ray|, the
+    mask of scored cells and the mask of cells whose residual moves."""
     ff = (c_r == FO) & (c_s == FO)
     fu = (c_r == FO) & (c_s == FU)
     uf = (c_r == FU) & (c_s == FO)
     with np.errstate(invalid="ignore"):
-        r = np.where(ff, dz, np.where(fu, np.minimum(dz, 0.0), np.where(uf, np.maximum(dz, 0.0), 0.0)))
+        e = dz * g
+        r = np.where(ff, e, np.where(fu, np.minimum(e, 0.0), np.where(uf, np.maximum(e, 0.0), 0.0)))
         moving = ff | (fu & (dz < 0)) | (uf & (dz > 0))
     scored = ff | fu | uf
     return np.where(scored, r, 0.0), scored, moving
@@ -258,28 +267,36 @@ def pixel_terms(rend, mesh_cls, scan_d, scan_c, cam, eps):
     with np.errstate(invalid="ignore"):
         dz = d_r - d_s
     s, cell = table1(c_r, c_s, dz, eps)
-    r, scored, moving = residual(c_r, c_s, dz)
-    rho = np.where(scored, 2.0 * np.minimum(r * r / (eps * eps), 1.0) - 1.0, 0.0)
-    active = scored & moving & (r * r < eps * eps)
     ray = rays(cam, pix)
     n = np.where(hit[:, None], rend["nrm"], 0.0)
     with np.errstate(invalid="ignore", divide="ignore"):
-        ndr = (n * ray).sum(-1)
-        P = np.where(hit, d_r, 0.0)[:, None] * ray
-        J = np.concatenate([-n, np.cross(n, P)], -1) / ndr[:, None]
+        nn = np.linalg.norm(n, axis=-1)
+        nh = n / np.where(nn > 0, nn, 1.0)[:, None]
+        ndr = (nh * ray).sum(-1)
+    g = np.abs(ndr)
+    r, scored, moving = residual(c_r, c_s, dz, g)
+    rho = np.where(scored, 2.0 * np.minimum(r * r / (eps * eps), 1.0) - 1.0, 0.0)
+    active = scored & moving & (r * r < eps * eps)
+    m = np.where((ndr < 0)[:, None], nh, -nh)
+    with np.errstate(invalid="ignore"):
+        Ps = np.where(np.isfinite(d_s), d_s, 0.0)[:, None] * ray
+        J = np.concatenate([m, np.cross(Ps, m)], -1)
     J = np.where(active[:, None], J, 0.0)
     return dict(s=s, cell=cell, rho=rho, r=r, active=active, J=J, dz=dz, c_r=c_r, c_s=c_s,
-                d_r=d_r, d_s=d_s)
+                d_r=d_r, d_s=d_s, g=g, ray_norm=np.linalg.norm(ray, axis=-1))
 
 
 def threshold_ties(terms, eps):
-    """Pixels whose Table I decision lies within the depth tolerance of a threshold."""
+    """Pixels whose Table I decision, or whether their E_soft residual is
+    inside the band |r| < eps, lies within the depth tolerance of a threshold."""
     with np.errstate(invalid="ignore"):
         scale = DEPTH_REL * np.fmax(np.abs(terms["d_r"]), np.abs(terms["d_s"]))
         dz = terms["dz"]
         ff = (terms["c_r"] == FO) & (terms["c_s"] == FO)
         one = ((terms["c_r"] == FO) & (terms["c_s"] == FU)) | ((terms["c_r"] == FU) & (terms["c_s"] == FO))
-        return (ff & (np.abs(np.abs(dz) - eps) <= scale)) | (one & (np.abs(dz) <= scale))
+        # |r| = |dz| g: a depth error of scale and a relative error of 1e-6 in g
+        band = (ff | one) & (np.abs(np.abs(terms["r"]) - eps) <= scale * terms["g"] + 1e-6 * np.abs(dz) * terms["ray_norm"])
+        return (ff & (np.abs(np.abs(dz) - eps) <= scale)) | (one & (np.abs(dz) <= scale)) | band
 
 
 def reduce_terms(terms, mask=None):
@@ -344,17 +361,23 @@ def gn_step(out, lam=0.0):
     return -np.linalg.solve(A, out["jtr"])
 
 
-def fd_jacobian(mesh, cam, T_wc, pixels, h=1e-4, mode="contract"):
-    """Central finite differences of the rendered depth with respect to the six
-    components of delta.  Returns (fd [N,6], stable [N] mask of pixels whose
-    winning triangle is the same at -h, 0 and +h on every axis)."""
-    base = render(mesh, cam, T_wc, pixels, mode)
+def fd_jacobian(mesh, cam, T_wc, pixels, scan_d, scan_c, h=1e-4, mode="contract"):
+    """Central finite differences of the unclamped E_soft residual e_p =
+    dz |n^ . ray| with respect to the six components of delta.  Returns
+    (fd [N,6], stable [N] mask of hit pixels whose winning triangle is the same
+    at -h, 0 and +h on every axis, terms at T_wc with every scored pixel inside
+    the band)."""
+    def terms(T):
+        rend = render(mesh, cam, T, pixels, mode)
+        t = pixel_terms(rend, mesh[2], scan_d, scan_c, cam, 1e30)
+        return rend, t, t["dz"] * t["g"]
+    base, t0, _ = terms(T_wc)
     fd = np.zeros((len(pixels), 6))
     stable = base["id"] >= 0
     for k in range(6):
         e = np.zeros(6); e[k] = h
-        rp = render(mesh, cam, retract(T_wc, e), pixels, mode)
-        rm = render(mesh, cam, retract(T_wc, -e), pixels, mode)
-        fd[:, k] = (rp["z"] - rm["z"]) / (2 * h)
+        rp, _, ep = terms(retract(T_wc, e))
+        rm, _, em = terms(retract(T_wc, -e))
+        fd[:, k] = (ep - em) / (2 * h)
         stable &= (rp["id"] == base["id"]) & (rm["id"] == base["id"])
-    return fd, stable, base
+    return fd, stable, t0

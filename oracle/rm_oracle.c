@@ -17,7 +17,9 @@
  *   or_meshify     -- the interface mesh of one range image: quads between
  *                     adjacent 2x2 (strided) pixels, free-unknown if a corner
  *                     is a no-return or a side exceeds the size threshold,
- *                     free-occupied otherwise.  Sec. IV-A.
+ *                     free-occupied otherwise.  Sec. IV-A.  Optionally each
+ *                     node's depth is first averaged over a window of
+ *                     pixels of similar depth (Sec. IV-C's blurring).
  *   or_render      -- the z-buffer R(T(X)) of Eq. (1) by brute force: for each
  *                     requested pixel, every triangle is tested for coverage
  *                     and the nearest depth wins.  The z-buffer holds
@@ -105,7 +107,7 @@ void or_scan_image(const float* depth, int32_t H, int32_t W, float z_min, float 
 #define OR_QBLOCK 8
 
 int64_t or_meshify(const float* depth, int32_t H, int32_t W, const or_camera* cam,
-                   const double* T, int32_t s, float z_min, float z_max, float max_edge,
+                   const double* T, int32_t s, int32_t R, float z_min, float z_max, float max_edge,
                    float* xyz, int32_t* tri, uint8_t* cls, int64_t cap_t, int64_t* n_v_out) {
     const int gh = (H + s - 1) / s, gw = (W + s - 1) / s;
     const int64_t nv = (int64_t)gh * gw;
@@ -117,7 +119,25 @@ int64_t or_meshify(const float* depth, int32_t H, int32_t W, const or_camera* ca
             const int k = px_class(z, z_min, z_max);
             kind[n] = (uint8_t)k;
             if (k == PX_DEAD) { xyz[3 * n] = xyz[3 * n + 1] = xyz[3 * n + 2] = NAN; continue; }
-            const double zd = (k == PX_NORET) ? (double)z_max : (double)z;
+            double zd = (k == PX_NORET) ? (double)z_max : (double)z;
+            if (k == PX_VALID && R > 0) {
+                /* noise reduction before meshing (Sec. IV-C suggests blurring
+                 * the depth images): mean of the valid window pixels within
+                 * 3% of the node pixel's depth, which keeps range edges */
+                double sum = 0.0;
+                int cnt = 0;
+                for (int y = i * s - R; y <= i * s + R; ++y)
+                    for (int x = j * s - R; x <= j * s + R; ++x) {
+                        if (y < 0 || y >= H || x < 0 || x >= W) continue;
+                        const float zn = depth[(int64_t)y * W + x];
+                        if (px_class(zn, z_min, z_max) != PX_VALID) continue;
+                        if (fabs((double)zn - (double)z) <= 0.03 * (double)z) {
+                            sum += (double)zn;
+                            cnt += 1;
+                        }
+                    }
+                zd = sum / (double)cnt;
+            }
             const double xc = zd * (((double)(j * s) - (double)cam->cx) / (double)cam->fx);
             const double yc = zd * (((double)(i * s) - (double)cam->cy) / (double)cam->fy);
             for (int r = 0; r < 3; ++r) {

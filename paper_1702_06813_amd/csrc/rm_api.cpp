@@ -500,7 +500,7 @@ int rm_scan_image(rm_ctx* ctx, const float* depth, int32_t height, int32_t width
 }
 
 int rm_mesh_from_range(rm_ctx* ctx, const float* depth, rm_camera cam, const double* T_wc, int32_t stride,
-                       float z_min, float z_max, float max_edge, float* xyz_out, int32_t* tri_out,
+                       int32_t smooth_radius, float z_min, float z_max, float max_edge, float* xyz_out, int32_t* tri_out,
                        uint8_t* cls_out, int64_t cap_t, int64_t* n_v_out, int64_t* n_t_out) {
     if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
     ctx->err.clear();
@@ -509,6 +509,8 @@ int rm_mesh_from_range(rm_ctx* ctx, const float* depth, rm_camera cam, const dou
     if (!depth || !T_wc || !xyz_out || !tri_out || !cls_out || !n_v_out || !n_t_out)
         return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
     if (stride < 1 || stride > 256) return fail(ctx, RM_ERR_INVALID_ARG, "stride %d outside 1..256", stride);
+    if (smooth_radius < 0 || smooth_radius > RM_MAX_SMOOTH_RADIUS)
+        return fail(ctx, RM_ERR_INVALID_ARG, "smooth_radius %d outside 0..%d", smooth_radius, RM_MAX_SMOOTH_RADIUS);
     if (!(z_min >= 0.0f && z_max > z_min && std::isfinite(z_max)))
         return fail(ctx, RM_ERR_INVALID_ARG, "need 0 <= z_min < z_max < inf");
     if (!(max_edge > 0.0f)) return fail(ctx, RM_ERR_INVALID_ARG, "max_edge must be positive");
@@ -527,7 +529,7 @@ int rm_mesh_from_range(rm_ctx* ctx, const float* depth, rm_camera cam, const dou
     const size_t o_tot = cv.take<int32_t>(1);
     rc = ensure_scratch(ctx, cv.off);
     if (rc) return rc;
-    RM_HIP(ctx, launch_meshify(ctx->stream, depth, cam, T_wc, stride, z_min, z_max, max_edge, xyz_out, tri_out,
+    RM_HIP(ctx, launch_meshify(ctx->stream, depth, cam, T_wc, stride, smooth_radius, z_min, z_max, max_edge, xyz_out, tri_out,
                                cls_out, cap_t, at<uint8_t>(ctx, o_kind), at<int32_t>(ctx, o_cnt),
                                at<int32_t>(ctx, o_off), at<int32_t>(ctx, o_tot)));
     RM_HIP(ctx, hipMemcpyAsync(ctx->pinned, at<int32_t>(ctx, o_tot), sizeof(int32_t), hipMemcpyDeviceToHost,

@@ -77,7 +77,7 @@ struct RasterArgs {
 hipError_t launch_scan_image(hipStream_t st, const float* depth, int32_t H, int32_t W, float z_min,
                              float z_max, float* d_out, uint8_t* c_out);
 hipError_t launch_meshify(hipStream_t st, const float* depth, rm_camera cam, const double* T,
-                          int32_t stride, float z_min, float z_max, float max_edge, float* xyz,
+                          int32_t stride, int32_t smooth_radius, float z_min, float z_max, float max_edge, float* xyz,
                           int32_t* tri, uint8_t* cls, int64_t cap_t, uint8_t* kind,
                           int32_t* block_counts, int32_t* block_offsets, int32_t* total);
 // Prepared-mesh buffer: [n_clusters] ClusterBounds, then (256-byte aligned)

@@ -29,17 +29,20 @@ __global__ void k_scan_image(const float* __restrict__ depth, int64_t n, float z
 
 struct Pose12 { double m[12]; };
 
-// Grid node (i, j) sits at pixel (j*s, i*s).  Back-projection in FP64 at the
-// node's depth (z_max for a no-return), world transform in FP64, one rounding
-// to f32 at the end.  Dead nodes get NaN.
-__global__ void k_mesh_nodes(const float* __restrict__ depth, int32_t H, int32_t W, int32_t s,
+// Grid node (i, j) sits at pixel (j*s, i*s).  A valid node's depth is the
+// FP64 mean of the valid pixels of the (2R+1)^2 window around it whose depth
+// is within RM_SMOOTH_REL of the node pixel's (R = 0: the node pixel).
+// Back-projection in FP64 at that depth (z_max for a no-return), world
+// transform in FP64, one rounding to f32 at the end.  Dead nodes get NaN.
+__global__ void k_mesh_nodes(const float* __restrict__ depth, int32_t H, int32_t W, int32_t s, int32_t R,
                              int32_t gh, int32_t gw, float fx, float fy, float cx, float cy,
                              Pose12 T, float z_min, float z_max, float* __restrict__ xyz,
                              uint8_t* __restrict__ kind) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)gh * gw) return;
     const int i = (int)(n / gw), j = (int)(n % gw);
-    const float z = depth[(int64_t)(i * s) * W + (int64_t)(j * s)];
+    const int py = i * s, px = j * s;
+    const float z = depth[(int64_t)py * W + px];
     const int k = range_class(z, z_min, z_max);
     kind[n] = (uint8_t)k;
     if (k == kDead) {
@@ -47,9 +50,21 @@ __global__ void k_mesh_nodes(const float* __restrict__ depth, int32_t H, int32_t
         xyz[3 * n] = q; xyz[3 * n + 1] = q; xyz[3 * n + 2] = q;
         return;
     }
-    const double zd = (k == kNoReturn) ? (double)z_max : (double)z;
-    const double xc = zd * (((double)(j * s) - (double)cx) / (double)fx);
-    const double yc = zd * (((double)(i * s) - (double)cy) / (double)fy);
+    double zd = (k == kNoReturn) ? (double)z_max : (double)z;
+    if (k == kValid && R > 0) {
+        const double zc = (double)z, tol = RM_SMOOTH_REL * zc;
+        double sum = 0.0;
+        int cnt = 0;
+        for (int yy = max(py - R, 0); yy <= min(py + R, H - 1); ++yy)
+            for (int xx = max(px - R, 0); xx <= min(px + R, W - 1); ++xx) {
+                const float zn = depth[(int64_t)yy * W + xx];
+                if (range_class(zn, z_min, z_max) != kValid) continue;
+                if (fabs((double)zn - zc) <= tol) { sum += (double)zn; ++cnt; }
+            }
+        zd = sum / (double)cnt;
+    }
+    const double xc = zd * (((double)px - (double)cx) / (double)fx);
+    const double yc = zd * (((double)py - (double)cy) / (double)fy);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const double w = ((T.m[4 * r] * xc + T.m[4 * r + 1] * yc) + T.m[4 * r + 2] * zd) + T.m[4 * r + 3];
@@ -222,8 +237,8 @@ hipError_t launch_scan_image(hipStream_t st, const float* depth, int32_t H, int3
 }
 
 hipError_t launch_meshify(hipStream_t st, const float* depth, rm_camera cam, const double* T,
-                          int32_t stride, float z_min, float z_max, float max_edge, float* xyz,
-                          int32_t* tri, uint8_t* cls, int64_t cap_t, uint8_t* kind,
+                          int32_t stride, int32_t smooth_radius, float z_min, float z_max, float max_edge,
+                          float* xyz, int32_t* tri, uint8_t* cls, int64_t cap_t, uint8_t* kind,
                           int32_t* block_counts, int32_t* block_offsets, int32_t* total) {
     const int32_t H = cam.height, W = cam.width;
     const int32_t gh = (H + stride - 1) / stride, gw = (W + stride - 1) / stride;
@@ -231,7 +246,7 @@ hipError_t launch_meshify(hipStream_t st, const float* depth, rm_camera cam, con
     for (int k = 0; k < 12; ++k) P.m[k] = T[k];
     const int64_t nn = (int64_t)gh * gw;
     hipLaunchKernelGGL(k_mesh_nodes, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, depth, H, W,
-                       stride, gh, gw, cam.fx, cam.fy, cam.cx, cam.cy, P, z_min, z_max, xyz, kind);
+                       stride, smooth_radius, gh, gw, cam.fx, cam.fy, cam.cx, cam.cy, P, z_min, z_max, xyz, kind);
     const int64_t nb = meshify_blocks(H, W, stride);
     const int bw = (gw - 1 + kQuadBlock - 1) / kQuadBlock;
     const double lim2 = (double)max_edge * (double)max_edge;

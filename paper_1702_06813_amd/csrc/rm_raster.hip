@@ -748,29 +748,33 @@ __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) acc.cnt[k] += cell == k;
         if (cell >= 6) continue;
+        // Camera-frame unit normal n of the winning triangle and g = |n . ray|:
+        // e = dz g is the scan point's signed distance from that triangle's plane.
+        const float* nw = a.nrm + 3 * (int64_t)id;
+        const float w0 = nw[0], w1 = nw[1], w2 = nw[2];
+        const float nx = fmaf(P.R[0][2], w2, fmaf(P.R[0][1], w1, P.R[0][0] * w0));
+        const float ny = fmaf(P.R[1][2], w2, fmaf(P.R[1][1], w1, P.R[1][0] * w0));
+        const float nz = fmaf(P.R[2][2], w2, fmaf(P.R[2][1], w1, P.R[2][0] * w0));
+        const float rx = ((float)x - cam.cx) * ifx, ry = ((float)y - cam.cy) * ify;
+        const float nr = fmaf(nx, rx, fmaf(ny, ry, nz));
+        const float e = dz * fabsf(nr);
         float r;
         bool moving;
-        if (cell <= 1) { r = dz; moving = true; }
-        else if (cell <= 3) { r = fminf(dz, 0.0f); moving = dz < 0.0f; }
-        else { r = fmaxf(dz, 0.0f); moving = dz > 0.0f; }
+        if (cell <= 1) { r = e; moving = true; }
+        else if (cell <= 3) { r = fminf(e, 0.0f); moving = dz < 0.0f; }
+        else { r = fmaxf(e, 0.0f); moving = dz > 0.0f; }
         const float q = r * r * ieps2;
         acc.e_soft += 2.0f * fminf(q, 1.0f) - 1.0f;
         if (MODE == kGrad && moving && r * r < eps * eps) {
-            // J = [-n ; n x P] / (n . r) from the winning triangle's camera-frame plane
-            const float* nw = a.nrm + 3 * (int64_t)id;
-            const float w0 = nw[0], w1 = nw[1], w2 = nw[2];
-            const float nx = fmaf(P.R[0][2], w2, fmaf(P.R[0][1], w1, P.R[0][0] * w0));
-            const float ny = fmaf(P.R[1][2], w2, fmaf(P.R[1][1], w1, P.R[1][0] * w0));
-            const float nz = fmaf(P.R[2][2], w2, fmaf(P.R[2][1], w1, P.R[2][0] * w0));
-            const float rx = ((float)x - cam.cx) * ifx, ry = ((float)y - cam.cy) * ify;
-            const float nr = fmaf(nx, rx, fmaf(ny, ry, nz));
-            const float inr = 1.0f / nr;
-            const float Px = z * rx, Py = z * ry, Pz = z;
+            // J = [m ; P_s x m]: m = n turned towards the camera, P_s = d_s ray
+            const float sg = nr < 0.0f ? 1.0f : -1.0f;
+            const float mx = sg * nx, my = sg * ny, mz = sg * nz;
+            const float Px = d_s * rx, Py = d_s * ry, Pz = d_s;
             float J[6];
-            J[0] = -nx * inr; J[1] = -ny * inr; J[2] = -nz * inr;
-            J[3] = (ny * Pz - nz * Py) * inr;
-            J[4] = (nz * Px - nx * Pz) * inr;
-            J[5] = (nx * Py - ny * Px) * inr;
+            J[0] = mx; J[1] = my; J[2] = mz;
+            J[3] = Py * mz - Pz * my;
+            J[4] = Pz * mx - Px * mz;
+            J[5] = Px * my - Py * mx;
             acc.n_active += 1;
 #pragma unroll
             for (int i = 0; i < 6; ++i) acc.jtr[i] = fmaf(r, J[i], acc.jtr[i]);

@@ -86,7 +86,7 @@ def load_library(path: Path | str | None = None):
             "rm_graph_launch": [V, V],
             "rm_graph_destroy": [V],
             "rm_scan_image": [V, V, I32, I32, F, F, V, V],
-            "rm_mesh_from_range": [V, V, CCamera, V, I32, F, F, F, V, V, V, I64, ctypes.POINTER(I64),
+            "rm_mesh_from_range": [V, V, CCamera, V, I32, I32, F, F, F, V, V, V, I64, ctypes.POINTER(I64),
                                    ctypes.POINTER(I64)],
             "rm_mesh_clusters": [V, ctypes.POINTER(CMesh), V],
             "rm_render_depth": [V, ctypes.POINTER(CMesh), CCamera, V, I32, V, V, V],
@@ -291,8 +291,11 @@ def _pose_host(T):
     return a, a.ctypes.data_as(ctypes.c_void_p)
 
 
-def mesh_from_range(depth: torch.Tensor, cam, T_wc, stride: int, z_min=0.5, z_max=8.0, max_edge=0.1) -> Mesh:
-    """rm_mesh_from_range: interface mesh of one range image (synchronizes)."""
+def mesh_from_range(depth: torch.Tensor, cam, T_wc, stride: int, z_min=0.5, z_max=8.0, max_edge=0.1,
+                    smooth_radius: int = 0) -> Mesh:
+    """rm_mesh_from_range: interface mesh of one range image (synchronizes).
+    smooth_radius R > 0 averages each node's depth over the (2R+1)^2 window
+    pixels within 3% of it before the surfaces are built."""
     _need(depth, torch.float32, "depth", None)
     H, W = depth.shape
     if (H, W) != (int(cam.height), int(cam.width)):
@@ -305,8 +308,8 @@ def mesh_from_range(depth: torch.Tensor, cam, T_wc, stride: int, z_min=0.5, z_ma
     cls = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
     nv, nt = ctypes.c_int64(), ctypes.c_int64()
     keep, pp = _pose_host(T_wc)
-    context(dev).call("rm_mesh_from_range", _ptr(depth), ccamera(cam), pp, stride, z_min, z_max, max_edge,
-                      _ptr(xyz), _ptr(tri), _ptr(cls), cap, ctypes.byref(nv), ctypes.byref(nt))
+    context(dev).call("rm_mesh_from_range", _ptr(depth), ccamera(cam), pp, stride, smooth_radius, z_min, z_max,
+                      max_edge, _ptr(xyz), _ptr(tri), _ptr(cls), cap, ctypes.byref(nv), ctypes.byref(nt))
     n = nt.value
     return Mesh(xyz, tri[:n], cls[:n])
 

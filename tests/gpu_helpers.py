@@ -34,7 +34,8 @@ def oracle_map(name: str):
     w = workload(name)
     if w.map_mesh is not None:
         return w.map_mesh
-    parts = [O.meshify(d, w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge) for T, d in zip(w.views, w.view_depths)]
+    parts = [O.meshify(d, w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge, w.smooth_radius)
+             for T, d in zip(w.views, w.view_depths)]
     xyz, tri, cls, off = [], [], [], 0
     for v, t, c in parts:
         xyz.append(v); tri.append(t + off); cls.append(c); off += len(v)

@@ -35,6 +35,7 @@ class Workload:
     view_depths: list = field(default_factory=list)  # [H,W] f32 range images
     stride: int = 1
     max_edge: float = 0.1
+    smooth_radius: int = 0             # node smoothing window half-width of the map meshing
 
 
 def _room_center(scene):
@@ -58,44 +59,44 @@ def tiny(seed: int = 0) -> Workload:
 def _meshified_room(seed, n_views, stride, cam, dropout=0.02, size=(6.0, 5.0, 2.8), n_boxes=16):
     door = S.Door(axis=0, side=1, lo=(1.5, 0.0), hi=(2.5, 2.1))
     scene = S.random_box_room(seed, size, n_boxes, doors=[door])
-    c = _room_center(scene)
-    views = S.circle_views(seed + 7, c, n_views)
+    views = S.inward_views(seed + 7, scene, n_views)
     depths = [S.range_image(scene, cam, T, seed * 1000 + k, noise_rel=0.01, dropout=dropout)
               for k, T in enumerate(views)]
     return scene, views, depths
 
 
 def _held_out_pose(scene, seed):
-    rng = np.random.default_rng(seed)
-    c = _room_center(scene)
-    ang = rng.uniform(0, 2 * np.pi)
-    pos = np.array([c[0] + np.cos(ang), c[1] + np.sin(ang), rng.uniform(1.2, 1.6)])
-    return S.look_pose(pos, ang + rng.uniform(-0.3, 0.3), rng.uniform(-0.2, 0.2)), rng
+    """A query pose of the same family as the map views, at an angle none of
+    them takes."""
+    T = S.inward_views(seed, scene, 1, phase=0.37)[0]
+    return T, np.random.default_rng(seed)
 
 
 def kinect(seed: int = 1, n_poses: int = 64) -> Workload:
-    """640x480 Kinect-like camera; map = 20 meshified views at stride 8
-    (about 186k triangles, free-occupied plus free-unknown); 64 candidates
-    drawn N(0, 3 cm) / N(0, 1.5 deg) per axis around the held-out truth."""
+    """640x480 Kinect-like camera; map = 20 meshified views at stride 8 with
+    node smoothing radius 4 (186,440 triangles, free-occupied plus
+    free-unknown); 64 candidates drawn N(0, 3 cm) / N(0, 1.5 deg) per axis
+    around the held-out truth."""
     cam = S.KINECT
     scene, views, depths = _meshified_room(seed, 20, 8, cam)
     T, rng = _held_out_pose(scene, seed + 11)
     depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.01, dropout=0.02)
     poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n_poses)])
     return Workload("kinect", cam, scene, T, depth, poses, views=views, view_depths=depths,
-                    stride=8, max_edge=0.1 * 8 / 2)
+                    stride=8, max_edge=0.1 * 8 / 2, smooth_radius=4)
 
 
 def differentiation(seed: int = 1, n_poses: int = 64) -> Workload:
-    """640x480; map = 27 meshified views at stride 4 (27 x 37,842 =
-    1,021,734 triangles); 64 candidates exactly 10 cm / 5 deg from the truth."""
+    """640x480; map = 27 meshified views at stride 4 with node smoothing
+    radius 4 (27 x 37,842 = 1,021,734 triangles); 64 candidates exactly
+    10 cm / 5 deg from the truth."""
     cam = S.KINECT
     scene, views, depths = _meshified_room(seed, 27, 4, cam)
     T, rng = _held_out_pose(scene, seed + 11)
     depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.01, dropout=0.02)
     poses = np.stack([S.perturb(T, rng, 0.10, np.deg2rad(5.0), fixed=True) for _ in range(n_poses)])
     return Workload("differentiation", cam, scene, T, depth, poses, views=views,
-                    view_depths=depths, stride=4, max_edge=0.1 * 4 / 2)
+                    view_depths=depths, stride=4, max_edge=0.1 * 4 / 2, smooth_radius=4)
 
 
 def wide(seed: int = 4, n_poses: int = 256, cell=0.018) -> Workload:

@@ -159,6 +159,26 @@ def circle_views(seed: int, center, n: int, radius=1.0, height=(1.2, 1.6),
     return out
 
 
+def inward_views(seed: int, scene: Scene, n: int, frac=0.75, height=(1.2, 1.7),
+                 pitch_deg=(-35.0, -10.0), aim_jitter=0.6, phase=0.0):
+    """``n`` poses spread over an ellipse at ``frac`` of the room's half
+    extents, each looking across the room at a point within ``aim_jitter`` m
+    of its centre, tilted down by a pitch drawn from ``pitch_deg``: every view
+    sees floor, far walls and boxes (no single plane fills the frame)."""
+    rng = np.random.default_rng(seed)
+    c = 0.5 * (scene.room_lo + scene.room_hi)
+    half = 0.5 * (scene.room_hi - scene.room_lo)
+    out = []
+    for k in range(n):
+        ang = 2 * np.pi * (k + phase) / n + rng.uniform(-0.1, 0.1)
+        pos = np.array([c[0] + frac * half[0] * np.cos(ang), c[1] + frac * half[1] * np.sin(ang),
+                        rng.uniform(*height)])
+        tgt = c[:2] + rng.uniform(-aim_jitter, aim_jitter, 2)
+        yaw = np.arctan2(tgt[1] - pos[1], tgt[0] - pos[0])
+        out.append(look_pose(pos, yaw, np.deg2rad(rng.uniform(*pitch_deg))))
+    return out
+
+
 # --------------------------------------------------------------------------
 # analytic range images
 # --------------------------------------------------------------------------
