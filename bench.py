@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-alignment", action="store_true", help="skip the batched-vs-plain alignment comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the pose-scoring path is built and "
@@ -127,6 +130,15 @@ def main():
     import paper_1702_06813_amd as rm
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+        return
     w, mesh, scan, T0 = build_inputs(rm, torch, dev)
     B = T0.shape[0]
     eps, lam = 0.1, 1e-3
@@ -206,7 +218,8 @@ def main():
                      "bytes_per_launch": bytes_launch, "visible_tris_per_pose": float(t_vis.mean())},
         "graph_ms_per_step": graph_ms,
     }
-    res["alignment"] = alignment_comparison(rm, torch, w, mesh, scan, T0)
+    if not args.no_alignment:
+        res["alignment"] = alignment_comparison(rm, torch, w, mesh, scan, T0)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a pixel sample")
         res["cpu_baseline"] = cpu_baseline(w, torch)

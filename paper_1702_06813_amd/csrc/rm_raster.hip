@@ -202,7 +202,9 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
             else if (dy[k] > 0) hi = fmin(hi, xc[k]);
             else empty |= E[k] < 0;                 // horizontal edge: the whole row is in or out
         }
-        const int xa = max(bx0, (int)ceil(lo - 1e-6)), xb = min(bx1, (int)floor(hi + 1e-6));
+        // lo >= bx0 and hi <= bx1 already; clamp the other side before converting
+        const int xa = max(bx0, (int)ceil(fmin(lo, (double)bx1 + 1.0) - 1e-6));
+        const int xb = min(bx1, (int)floor(fmax(hi, (double)bx0 - 1.0) + 1e-6));
         if (!empty && xa <= xb) {
             int64_t e0 = E[0] - 256 * (int64_t)dy[0] * (xa - bx0);
             int64_t e1 = E[1] - 256 * (int64_t)dy[1] * (xa - bx0);
