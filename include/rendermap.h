@@ -153,8 +153,10 @@ const char* rm_last_error(const rm_ctx* ctx);
  * rm_autotune is on, 64x32 otherwise).  Results do not depend on it. */
 int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
 /* Turns the tile autotuner on or off.  When on, the first call for a new
- * (image size, pose count, triangle count) times every tile shape on the
- * call's own inputs and keeps the fastest for later calls of that shape. */
+ * (image size, pose count, triangle count) times the tile shapes on the
+ * call's own inputs, largest first, stopping at the first shape more than
+ * 25% slower than the best so far, and keeps the fastest for later calls of
+ * that shape. */
 int rm_autotune(rm_ctx* ctx, int32_t enable);
 /* Current tile choice for a shape (after autotuning), for reporting. */
 int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int64_t n_tris,

@@ -142,7 +142,10 @@ bool valid_tile(int w, int h) {
     return (w == 16 && h == 16) || (w == 32 && h == 32) || (w == 64 && h == 32);
 }
 
-const int kTiles[3][2] = {{16, 16}, {32, 32}, {64, 32}};
+// Autotune candidates, largest first: each step down quadruples or doubles
+// the per-pose tile records and bins, so the search stops at the first shape
+// that is clearly slower than the best so far.
+const int kTiles[3][2] = {{64, 32}, {32, 32}, {16, 16}};
 
 // Fills the scan descriptors and counts items and partial records.
 void plan(BatchDesc& bd, int tw, int th) {
@@ -285,7 +288,7 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
         RM_HIP(ctx, hipEventCreate(&ctx->ev1));
     }
     float best = 1e30f;
-    int bi = 1;
+    int bi = 0;
     for (int k = 0; k < 3; ++k) {
         // one warm-up and one timed pass per shape
         for (int rep = 0; rep < 2; ++rep) {
@@ -299,6 +302,7 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
         float ms = 0.0f;
         RM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         if (ms < best) { best = ms; bi = k; }
+        else if (ms > 1.25f * best) break;
     }
     ctx->tuned[key] = {kTiles[bi][0], kTiles[bi][1]};
     return run_pass(ctx, mesh, bd, kTiles[bi][0], kTiles[bi][1], mode, T_wc, eps, out, depth_out, tri_out, cls_out);

@@ -86,9 +86,9 @@ constexpr uint64_t kEmptyKey = ~0ull;
 // thin triangles keep their depth to ~1e-7 relative.
 struct WPlane { double a, b, e; };
 
-__device__ __forceinline__ WPlane depth_plane(const PoseF& P, const float* __restrict__ nw, float x0, float y0,
+__device__ __forceinline__ WPlane depth_plane(const PoseF& P, float nw0, float nw1, float nw2, float x0, float y0,
                                               float z0, double ifx, double ify) {
-    const double n0 = nw[0], n1 = nw[1], n2 = nw[2];
+    const double n0 = nw0, n1 = nw1, n2 = nw2;
     const double c = n0 * ((double)x0 - P.t[0]) + n1 * ((double)y0 - P.t[1]) + n2 * ((double)z0 - P.t[2]);
     const double ic = 1.0 / c;
     // camera-frame normal with the f32-rounded rotation (a 6e-8 rotation of the
@@ -108,10 +108,15 @@ struct Tile {
 };
 
 
+// Occlusion margin: a row of a triangle is skipped when its nearest depth,
+// scaled by this factor, is still farther than the farthest key of the row
+// snapshot (far more than the rounding between the FP64 plane and the f32 key).
+constexpr double kOccMargin = 1.0 + 1e-6;
+
 // Small (sub-)triangles are rasterized by their own thread over the pixel
 // centres of their bounding box inside the tile (int32 edge functions).
-__device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const Tile& tl, const int X[3],
-                                             const int Y[3], int px0, int px1, int py0, int py1,
+__device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const Tile& tl, const float* rmin,
+                                             const int X[3], const int Y[3], int px0, int px1, int py0, int py1,
                                              const WPlane& pl, double cx, double cy, float w_far, uint32_t id) {
     int E[3], sx[3], sy[3];
 #pragma unroll
@@ -128,7 +133,11 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
         int e0 = E[0], e1 = E[1], e2 = E[2];
         double w = wrow;
         uint64_t* row = keys + (y - tl.y0) * tile_w - tl.x0;
-        for (int x = px0; x <= px1; ++x) {
+        // the plane's nearest point over the row's columns is behind everything
+        // visible in this row: every atomic below would leave the keys unchanged
+        const double wn = fmax(wrow, fma(pl.a, (double)(px1 - px0), wrow));
+        const int xend = wn * kOccMargin < (double)rmin[y - tl.y0] ? px0 - 1 : px1;
+        for (int x = px0; x <= xend; ++x) {
             {   // branch-free: an uncovered pixel offers the empty key, which changes nothing
                 const float wf = (float)w;
                 const bool cov = ((e0 | e1 | e2) >= 0) & (wf >= w_far);
@@ -175,8 +184,9 @@ struct FatQueue {
 
 // Rows r0..r1 (tile-relative) of one sub-triangle with tile-relative snapped
 // vertices (X, Y), edge slopes m, depth plane and tile-relative column range.
-__device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Tile& tl, const int X[3],
-                                            const int Y[3], const double m[3], double pa, double pb, double pe,
+__device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Tile& tl, const float* rmin,
+                                            const int X[3], const int Y[3], const double m[3], double pa, double pb,
+                                            double pe,
                                             uint32_t id, int bx0, int bx1, int r0, int r1, double cx, double cy,
                                             float w_far) {
     int64_t E[3];
@@ -205,11 +215,11 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
         // lo >= bx0 and hi <= bx1 already; clamp the other side before converting
         const int xa = max(bx0, (int)ceil(fmin(lo, (double)bx1 + 1.0) - 1e-6));
         const int xb = min(bx1, (int)floor(fmax(hi, (double)bx0 - 1.0) + 1e-6));
-        if (!empty && xa <= xb) {
+        double w = fma(pa, (double)(xa - bx0), wrow);
+        if (!empty && xa <= xb && fmax(w, fma(pa, (double)(xb - xa), w)) * kOccMargin >= (double)rmin[r]) {
             int64_t e0 = E[0] - 256 * (int64_t)dy[0] * (xa - bx0);
             int64_t e1 = E[1] - 256 * (int64_t)dy[1] * (xa - bx0);
             int64_t e2 = E[2] - 256 * (int64_t)dy[2] * (xa - bx0);
-            double w = fma(pa, (double)(xa - bx0), wrow);
             uint64_t* row = keys + r * tile_w;
             for (int x = xa; x <= xb; ++x) {
                 {
@@ -228,8 +238,8 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
 }
 
 template <int TW, int TH>
-__device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const Tile& tl, double cx, double cy,
-                                             float w_far) {
+__device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const Tile& tl, const float* rmin,
+                                             double cx, double cy, float w_far) {
     const int nj = q.njobs;
     for (int j = threadIdx.x; j < nj; j += kWG) {
         const int rec = q.job[j];
@@ -240,7 +250,7 @@ __device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const 
         const int X[3] = {q.X[0][b], q.X[1][b], q.X[2][b]};
         const int Y[3] = {q.Y[0][b], q.Y[1][b], q.Y[2][b]};
         const double m[3] = {q.m[0][b], q.m[1][b], q.m[2][b]};
-        raster_rows(keys, TW, tl, X, Y, m, q.pa[b], q.pb[b], q.pe[b], q.id[b], (int)(box & 0xff),
+        raster_rows(keys, TW, tl, rmin, X, Y, m, q.pa[b], q.pb[b], q.pe[b], q.id[b], (int)(box & 0xff),
                     (int)((box >> 8) & 0xff), r0, r1, cx, cy, w_far);
     }
 }
@@ -276,10 +286,13 @@ __device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Ti
 struct Queues {
     BigQueue big;
     FatQueue fat;
+    // per tile row, the farthest w = 1/z held by its keys (0 if a pixel is
+    // empty) at the start of the round; two buffers, one filled per round
+    float rowmin[2][32];
 };
 
-__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const Tile& tl, const CamF& cam,
-                                         float3 A, float3 B, float3 C, const WPlane& pl, float w_far,
+__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const float* rmin, const Tile& tl,
+                                         const CamF& cam, float3 A, float3 B, float3 C, const WPlane& pl, float w_far,
                                          uint32_t id) {
     int X[3], Y[3];
     if (!snap(cam, A, X[0], Y[0]) || !snap(cam, B, X[1], Y[1]) || !snap(cam, C, X[2], Y[2])) return;
@@ -299,7 +312,7 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     const uint32_t box = (uint32_t)(px0 - tl.x0) | ((uint32_t)(px1 - tl.x0) << 8) | ((uint32_t)(py0 - tl.y0) << 16) |
                          ((uint32_t)(py1 - tl.y0) << 24);
     if (boxpx <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
-        raster_small(keys, tile_w, tl, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far, id);
+        raster_small(keys, tile_w, tl, rmin, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far, id);
         return;
     }
     // fat: many covered pixels in the tile and thick (2 area / longest edge > 8 px)
@@ -342,7 +355,7 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     }
     const int k = atomicAdd(&Q.big.n, 1);
     if (k >= kQCap) {                          // queue full: this thread walks the rows itself
-        raster_rows(keys, tile_w, tl, Xr, Yr, m, pl.a, pl.b, pl.e, id, px0 - tl.x0, px1 - tl.x0, py0 - tl.y0,
+        raster_rows(keys, tile_w, tl, rmin, Xr, Yr, m, pl.a, pl.b, pl.e, id, px0 - tl.x0, px1 - tl.x0, py0 - tl.y0,
                     py1 - tl.y0, (double)cam.cx, (double)cam.cy, w_far);
         return;
     }
@@ -360,25 +373,51 @@ __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
     return k == 0 ? a : (k == 1 ? b : c);
 }
 
+// A mesh triangle's inputs, gathered ahead of use: the rounds of a tile
+// pipeline these loads (bin entry, then vertex indices, then vertices and
+// normal) so that the dependent global gathers overlap earlier rounds' work.
+struct TriIn {
+    int32_t t;             // triangle id, -1 for none
+    float v[9];            // world vertices
+    float n[3];            // world unit normal
+};
+
+__device__ __forceinline__ void load_indices(const int32_t* __restrict__ tri, uint32_t vmax, int32_t t,
+                                             uint32_t I[3]) {
+    if (t < 0) { I[0] = I[1] = I[2] = 0; return; }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) I[k] = min((uint32_t)tri[3 * (int64_t)t + k], vmax);
+}
+
+__device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, const float* __restrict__ nrm, int32_t t,
+                                              const uint32_t I[3], TriIn& o) {
+    o.t = t;
+    if (t < 0) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o.v[3 * k] = xyz[3 * (int64_t)I[k]];
+        o.v[3 * k + 1] = xyz[3 * (int64_t)I[k] + 1];
+        o.v[3 * k + 2] = xyz[3 * (int64_t)I[k] + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.n[k] = nrm[3 * (int64_t)t + k];
+}
+
 // Whole contract for one mesh triangle: transform, far cull, near clip into
 // at most two sub-triangles (same id), setup and rasterization.
-__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queues& q, const Tile& tl,
-                                                const CamF& cam, double ifx, double ify, float w_far,
-                                                const PoseF& P, const float* __restrict__ xyz,
-                                                const int32_t* __restrict__ tri, const float* __restrict__ nrm,
-                                                uint32_t vmax, int64_t t) {
-    const uint32_t i0 = min((uint32_t)tri[3 * t], vmax), i1 = min((uint32_t)tri[3 * t + 1], vmax),
-                   i2 = min((uint32_t)tri[3 * t + 2], vmax);
-    const float x0 = xyz[3 * (int64_t)i0], y0 = xyz[3 * (int64_t)i0 + 1], z0 = xyz[3 * (int64_t)i0 + 2];
+__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queues& q, const float* rmin,
+                                                const Tile& tl, const CamF& cam, double ifx, double ify, float w_far,
+                                                const PoseF& P, const TriIn& in) {
+    const float x0 = in.v[0], y0 = in.v[1], z0 = in.v[2];
     const float3 V0 = cam_contract(P, x0, y0, z0);
-    const float3 V1 = cam_contract(P, xyz[3 * (int64_t)i1], xyz[3 * (int64_t)i1 + 1], xyz[3 * (int64_t)i1 + 2]);
-    const float3 V2 = cam_contract(P, xyz[3 * (int64_t)i2], xyz[3 * (int64_t)i2 + 1], xyz[3 * (int64_t)i2 + 2]);
+    const float3 V1 = cam_contract(P, in.v[3], in.v[4], in.v[5]);
+    const float3 V2 = cam_contract(P, in.v[6], in.v[7], in.v[8]);
     if (V0.z > cam.zf && V1.z > cam.zf && V2.z > cam.zf) return;
     const bool in0 = V0.z >= cam.zn, in1 = V1.z >= cam.zn, in2 = V2.z >= cam.zn;
     const int nin = (int)in0 + (int)in1 + (int)in2;
     if (nin == 0) return;
-    const WPlane pl = depth_plane(P, nrm + 3 * t, x0, y0, z0, ifx, ify);
-    const uint32_t id = (uint32_t)t;
+    const WPlane pl = depth_plane(P, in.n[0], in.n[1], in.n[2], x0, y0, z0, ifx, ify);
+    const uint32_t id = (uint32_t)in.t;
     // near-plane clip into at most two sub-triangles; one emit call site keeps
     // a single copy of the setup and rasterization code
     float3 A0 = V0, B0 = V1, C0 = V2, A1 = V0, B1 = V1, C1 = V2;
@@ -403,7 +442,7 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
 #pragma unroll 1
     for (int sub = 0; sub < nsub; ++sub) {
         const float3 A = sub ? A1 : A0, B = sub ? B1 : B0, C = sub ? C1 : C0;
-        emit_tri(keys, tile_w, q, tl, cam, A, B, C, pl, w_far, id);
+        emit_tri(keys, tile_w, q, rmin, tl, cam, A, B, C, pl, w_far, id);
     }
 }
 
@@ -660,7 +699,7 @@ __device__ __forceinline__ bool decode_item(const BatchDesc& bd, ItemInfo& it) {
 }
 
 template <int TW, int TH, int MODE>
-__global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
+__global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
     __shared__ uint64_t keys[TW * TH];
     __shared__ Queues q;
     __shared__ float red[kWG / 64][kRecFields];
@@ -694,22 +733,50 @@ __global__ void __launch_bounds__(kWG) k_raster(BatchDesc bd, RasterArgs a) {
     const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
     const uint32_t* bin = a.bins + it.rec * (int64_t)a.bin_cap;
     const int nr = use_bin ? (ns + nb + kWG - 1) / kWG : nvis;
-    for (int r = 0; r < nr; ++r) {
-        if (tid == 0) { q.big.n = 0; q.big.njobs = 0; q.fat.n = 0; }
-        __syncthreads();
-        int64_t t = -1;
+    auto entry = [&](int r) -> int32_t {
+        if (r >= nr) return -1;
         if (use_bin) {
             const int i = r * kWG + tid;
-            if (i < ns + nb) t = i < ns ? bin[i] : bin[a.bin_cap - 1 - (i - ns)];
-        } else {
-            t = (int64_t)vis[r].x * kClusterTris + tid;
-            if (t >= a.n_tris) t = -1;
+            if (i >= ns + nb) return -1;
+            return (int32_t)(i < ns ? bin[i] : bin[a.bin_cap - 1 - (i - ns)]);
         }
-        if (t >= 0) raster_triangle(keys, TW, q, tl, cam, difx, dify, w_far, P, a.xyz, a.tri, a.nrm, a.vmax, t);
+        const int64_t t = (int64_t)vis[r].x * kClusterTris + tid;
+        return t < a.n_tris ? (int32_t)t : -1;
+    };
+    // three-stage gather pipeline: round r processes vertices loaded during
+    // round r-1 from indices loaded during r-2 from a bin entry read in r-3
+    TriIn cur, nxt;
+    uint32_t I1[3], I2[3];
+    int32_t t1 = entry(0), t2, t3;
+    load_indices(a.tri, a.vmax, t1, I1);
+    load_vertices(a.xyz, a.nrm, t1, I1, cur);
+    t1 = entry(1);
+    load_indices(a.tri, a.vmax, t1, I1);
+    t2 = entry(2);
+    if (tid < 32) q.rowmin[0][tid] = 0.0f;           // round 0 sees an empty buffer
+    for (int r = 0; r < nr; ++r) {
+        if (tid == 0) { q.big.n = 0; q.big.njobs = 0; q.fat.n = 0; }
+        if (tid < TH) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
+        const float* rmin = q.rowmin[r & 1];
+        load_vertices(a.xyz, a.nrm, t1, I1, nxt);
+        load_indices(a.tri, a.vmax, t2, I2);
+        t3 = entry(r + 3);
         __syncthreads();
-        if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, dcx, dcy, w_far);
+        if (cur.t >= 0) raster_triangle(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
+        __syncthreads();
+        if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
         if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, dcx, dcy, w_far);
         __syncthreads();
+        // row snapshot for the next round (w >= 0, so its bits order like its value)
+        if (r + 1 < nr)
+            for (int p = tid; p < TW * TH; p += kWG) {
+                const uint32_t wb = ~(uint32_t)(keys[p] >> 32);
+                atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][p / TW], wb);
+            }
+        cur = nxt;
+        t1 = t2;
+        I1[0] = I2[0]; I1[1] = I2[1]; I1[2] = I2[2];
+        t2 = t3;
     }
 
     // ---------------------------------------------------------------- resolve
