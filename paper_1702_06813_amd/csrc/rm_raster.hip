@@ -256,8 +256,8 @@ __device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const 
 }
 
 template <int TW, int TH>
-__device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Tile& tl, double cx, double cy,
-                                           float w_far) {
+__device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Tile& tl, const float* rmin,
+                                           double cx, double cy, float w_far) {
     const int nq = min(q.n, kFatCap);
     for (int b = 0; b < nq; ++b) {
         const uint32_t box = q.box[b];
@@ -266,6 +266,10 @@ __device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Ti
         for (int p = threadIdx.x + by0 * TW; p < (by1 + 1) * TW; p += kWG) {
             const int y = p / TW, x = p % TW;              // TW is a power of two
             if (x < bx0 || x > bx1) continue;
+            // farther than the row's farthest key at the round start: the
+            // atomic could not change the pixel, covered or not
+            const float wf = (float)fma(q.pb[b], (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
+            if (wf < rmin[y] || wf < w_far) continue;
             const int ry = y - by0, rx = x - bx0;
             bool in = true;
 #pragma unroll
@@ -273,10 +277,7 @@ __device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Ti
                 const int64_t e = q.E[k][b] + 256 * ((int64_t)q.dx[k][b] * ry - (int64_t)q.dy[k][b] * rx);
                 in &= e >= 0;
             }
-            if (!in) continue;
-            const float wf = (float)fma(q.pb[b], (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
-            if (wf >= w_far)
-                atomicMin((unsigned long long*)(keys + y * TW + x), (unsigned long long)pack_key(wf, q.id[b]));
+            if (in) atomicMin((unsigned long long*)(keys + y * TW + x), (unsigned long long)pack_key(wf, q.id[b]));
         }
     }
 }
@@ -287,8 +288,9 @@ struct Queues {
     BigQueue big;
     FatQueue fat;
     // per tile row, the farthest w = 1/z held by its keys (0 if a pixel is
-    // empty) at the start of the round; two buffers, one filled per round
-    float rowmin[2][32];
+    // empty) at the start of the round, and at [32] the tile's farthest; two
+    // buffers, one filled per round
+    float rowmin[2][33];
 };
 
 __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const float* rmin, const Tile& tl,
@@ -417,6 +419,13 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
     const int nin = (int)in0 + (int)in1 + (int)in2;
     if (nin == 0) return;
     const WPlane pl = depth_plane(P, in.n[0], in.n[1], in.n[2], x0, y0, z0, ifx, ify);
+    if (nin == 3) {
+        // 1/z over the triangle peaks at its nearest vertex; one pixel of plane
+        // extrapolation covers the snapping.  Behind the tile's farthest key at
+        // the round start, no pixel of the triangle can change.
+        const double wv = 1.0 / (double)fminf(V0.z, fminf(V1.z, V2.z)) + fabs(pl.a) + fabs(pl.b);
+        if (wv * 1.00001 < (double)rmin[32]) return;
+    }
     const uint32_t id = (uint32_t)in.t;
     // near-plane clip into at most two sub-triangles; one emit call site keeps
     // a single copy of the setup and rasterization code
@@ -753,10 +762,10 @@ __global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
     t1 = entry(1);
     load_indices(a.tri, a.vmax, t1, I1);
     t2 = entry(2);
-    if (tid < 32) q.rowmin[0][tid] = 0.0f;           // round 0 sees an empty buffer
+    if (tid < 33) q.rowmin[0][tid] = 0.0f;           // round 0 sees an empty buffer
     for (int r = 0; r < nr; ++r) {
         if (tid == 0) { q.big.n = 0; q.big.njobs = 0; q.fat.n = 0; }
-        if (tid < TH) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
+        if (tid < 33) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
         const float* rmin = q.rowmin[r & 1];
         load_vertices(a.xyz, a.nrm, t1, I1, nxt);
         load_indices(a.tri, a.vmax, t2, I2);
@@ -765,14 +774,19 @@ __global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
         if (cur.t >= 0) raster_triangle(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
         __syncthreads();
         if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
-        if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, dcx, dcy, w_far);
+        if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, rmin, dcx, dcy, w_far);
         __syncthreads();
-        // row snapshot for the next round (w >= 0, so its bits order like its value)
-        if (r + 1 < nr)
+        // row and tile snapshot for the next round (w >= 0, so its bits order
+        // like its value)
+        if (r + 1 < nr) {
+            uint32_t tmin = 0x7f800000u;
             for (int p = tid; p < TW * TH; p += kWG) {
                 const uint32_t wb = ~(uint32_t)(keys[p] >> 32);
                 atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][p / TW], wb);
+                tmin = min(tmin, wb);
             }
+            atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][32], tmin);
+        }
         cur = nxt;
         t1 = t2;
         I1[0] = I2[0]; I1[1] = I2[1]; I1[2] = I2[2];
