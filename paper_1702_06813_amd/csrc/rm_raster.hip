@@ -112,6 +112,17 @@ struct Tile {
 // scaled by this factor, is still farther than the farthest key of the row
 // snapshot (far more than the rounding between the FP64 plane and the f32 key).
 constexpr double kOccMargin = 1.0 + 1e-6;
+// The depth snapshot keeps one value per kSeg-pixel segment of each tile row
+// (index row * kSegs + x / kSeg) and the tile's farthest at kSnapTile.
+constexpr int kSeg = 16, kSegs = 4, kSnapTile = 32 * kSegs;
+
+// Farthest snapshot w over the segments that columns [x0, x1] of row y touch.
+__device__ __forceinline__ float snap_min(const float* rmin, int y, int x0, int x1) {
+    const float* r = rmin + y * kSegs;
+    float m = r[x0 / kSeg];
+    for (int s = x0 / kSeg + 1; s <= x1 / kSeg; ++s) m = fminf(m, r[s]);
+    return m;
+}
 
 // Small (sub-)triangles are rasterized by their own thread over the pixel
 // centres of their bounding box inside the tile (int32 edge functions).
@@ -136,7 +147,7 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
         // the plane's nearest point over the row's columns is behind everything
         // visible in this row: every atomic below would leave the keys unchanged
         const double wn = fmax(wrow, fma(pl.a, (double)(px1 - px0), wrow));
-        const int xend = wn * kOccMargin < (double)rmin[y - tl.y0] ? px0 - 1 : px1;
+        const int xend = wn * kOccMargin < (double)snap_min(rmin, y - tl.y0, px0 - tl.x0, px1 - tl.x0) ? px0 - 1 : px1;
         for (int x = px0; x <= xend; ++x) {
             {   // branch-free: an uncovered pixel offers the empty key, which changes nothing
                 const float wf = (float)w;
@@ -216,7 +227,7 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
         const int xa = max(bx0, (int)ceil(fmin(lo, (double)bx1 + 1.0) - 1e-6));
         const int xb = min(bx1, (int)floor(fmax(hi, (double)bx0 - 1.0) + 1e-6));
         double w = fma(pa, (double)(xa - bx0), wrow);
-        if (!empty && xa <= xb && fmax(w, fma(pa, (double)(xb - xa), w)) * kOccMargin >= (double)rmin[r]) {
+        if (!empty && xa <= xb && fmax(w, fma(pa, (double)(xb - xa), w)) * kOccMargin >= (double)snap_min(rmin, r, xa, xb)) {
             int64_t e0 = E[0] - 256 * (int64_t)dy[0] * (xa - bx0);
             int64_t e1 = E[1] - 256 * (int64_t)dy[1] * (xa - bx0);
             int64_t e2 = E[2] - 256 * (int64_t)dy[2] * (xa - bx0);
@@ -269,7 +280,7 @@ __device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Ti
             // farther than the row's farthest key at the round start: the
             // atomic could not change the pixel, covered or not
             const float wf = (float)fma(q.pb[b], (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
-            if (wf < rmin[y] || wf < w_far) continue;
+            if (wf < rmin[y * kSegs + x / kSeg] || wf < w_far) continue;
             const int ry = y - by0, rx = x - bx0;
             bool in = true;
 #pragma unroll
@@ -287,10 +298,10 @@ __device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Ti
 struct Queues {
     BigQueue big;
     FatQueue fat;
-    // per tile row, the farthest w = 1/z held by its keys (0 if a pixel is
-    // empty) at the start of the round, and at [32] the tile's farthest; two
-    // buffers, one filled per round
-    float rowmin[2][33];
+    // per kSeg-pixel segment of each tile row, the farthest w = 1/z held by
+    // its keys (0 if a pixel is empty) at the start of the round, and at
+    // kSnapTile the tile's farthest; two buffers, one filled per round
+    float rowmin[2][kSnapTile + 1];
 };
 
 __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const float* rmin, const Tile& tl,
@@ -424,7 +435,7 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
         // extrapolation covers the snapping.  Behind the tile's farthest key at
         // the round start, no pixel of the triangle can change.
         const double wv = 1.0 / (double)fminf(V0.z, fminf(V1.z, V2.z)) + fabs(pl.a) + fabs(pl.b);
-        if (wv * 1.00001 < (double)rmin[32]) return;
+        if (wv * 1.00001 < (double)rmin[kSnapTile]) return;
     }
     const uint32_t id = (uint32_t)in.t;
     // near-plane clip into at most two sub-triangles; one emit call site keeps
@@ -762,10 +773,10 @@ __global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
     t1 = entry(1);
     load_indices(a.tri, a.vmax, t1, I1);
     t2 = entry(2);
-    if (tid < 33) q.rowmin[0][tid] = 0.0f;           // round 0 sees an empty buffer
+    if (tid <= kSnapTile) q.rowmin[0][tid] = 0.0f;   // round 0 sees an empty buffer
     for (int r = 0; r < nr; ++r) {
         if (tid == 0) { q.big.n = 0; q.big.njobs = 0; q.fat.n = 0; }
-        if (tid < 33) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
+        if (tid <= kSnapTile) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
         const float* rmin = q.rowmin[r & 1];
         load_vertices(a.xyz, a.nrm, t1, I1, nxt);
         load_indices(a.tri, a.vmax, t2, I2);
@@ -782,10 +793,10 @@ __global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
             uint32_t tmin = 0x7f800000u;
             for (int p = tid; p < TW * TH; p += kWG) {
                 const uint32_t wb = ~(uint32_t)(keys[p] >> 32);
-                atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][p / TW], wb);
+                atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][(p / TW) * kSegs + (p % TW) / kSeg], wb);
                 tmin = min(tmin, wb);
             }
-            atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][32], tmin);
+            atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][kSnapTile], tmin);
         }
         cur = nxt;
         t1 = t2;
