@@ -290,9 +290,13 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
     float best = 1e30f;
     int bi = 0;
     for (int k = 0; k < 3; ++k) {
-        // one warm-up and one timed pass per shape
+        // one warm-up and one timed pass per shape; the warm-up's largest bin
+        // is read back first so that the timed pass runs with bins that fit
         for (int rep = 0; rep < 2; ++rep) {
-            if (rep == 1) RM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            if (rep == 1) {
+                if (ctx->bin_pending) RM_HIP(ctx, hipEventSynchronize(ctx->bin_ev));
+                RM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            }
             int rc = run_pass(ctx, mesh, bd, kTiles[k][0], kTiles[k][1], mode, T_wc, eps, out, depth_out, tri_out,
                               cls_out);
             if (rc) return rc;
