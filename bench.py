@@ -30,6 +30,21 @@ if ROOT not in sys.path:
 
 METRIC = "pose cost+grad evals/s @640x480, 1M-tri mesh; scans aligned/s vs plain form"
 HBM_PEAK_GBS = 8000.0
+# DRAM bytes of one rasterizer launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
+# scaled by a plain-copy calibration (profiles/k_raster_differentiation.md);
+# valid only for the rasterizer source and tile they were taken with.
+PROFILED_TRAFFIC = {"rm_raster_sha256_16": "d54ba78d9366244a", "tile": [32, 32], "bytes_per_launch": 566.9e6}
+
+
+def profiled_traffic(tile):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1702_06813_amd", "csrc", "rm_raster.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    ok = h == PROFILED_TRAFFIC["rm_raster_sha256_16"] and list(tile) == PROFILED_TRAFFIC["tile"]
+    return PROFILED_TRAFFIC["bytes_per_launch"] if ok else None
 
 
 def log(msg):
@@ -195,6 +210,7 @@ def main():
     graph_ms = (time.perf_counter() - tg0) / args.steps * 1e3
     log(f"graph replay: {graph_ms:.3f} ms/step")
 
+    tile = list(ctx.get_tile(W, H, B, mesh.n_tris))
     res = {
         "metric": METRIC,
         "value": B * args.steps / wall,
@@ -211,9 +227,9 @@ def main():
         "config": {"workload": "differentiation: 640x480 scan vs 1,021,734-triangle meshified room map, "
                                "64 poses per launch, cost + se(3) gradient + JtJ/Jtr + LM pose update",
                    "global_batch": B, "image": [W, H], "n_tris": mesh.n_tris, "eps": eps,
-                   "tile": list(ctx.get_tile(W, H, B, mesh.n_tris))},
+                   "tile": tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(tile),
                      "kernel": "k_raster (grad)", "avg_launch_ms": avg_s * 1e3,
                      "bytes_per_launch": bytes_launch, "visible_tris_per_pose": float(t_vis.mean())},
         "graph_ms_per_step": graph_ms,
