@@ -18,7 +18,11 @@
  *     owns every buffer; the library owns only the scratch inside rm_ctx and
  *     keeps no caller pointer after a call returns.
  *   - Work is enqueued asynchronously on the context stream (rm_ctx_set_stream)
- *     and no call synchronizes, except rm_mesh_from_range (it returns counts).
+ *     and no call synchronizes, except rm_mesh_from_range (it returns counts)
+ *     and the first call of a new launch shape (scan sizes, pose count,
+ *     triangle count, tile) outside graph capture, which waits once for the
+ *     binning pass to size its screen-tile bins; capture a shape only after
+ *     one uncaptured call of it.
  *   - Arguments are validated on the host before anything is launched;
  *     invalid arguments return RM_ERR_INVALID_ARG and launch nothing.
  *   - Device arrays are dense and row-major.  Images are [H][W] with pixel

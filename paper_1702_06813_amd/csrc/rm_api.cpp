@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -35,6 +36,8 @@ struct rm_ctx {
     int32_t bin_cap = 1024;
     hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bin
     bool bin_pending = false;
+    // launch shapes whose bins were sized by a synchronous check after binning
+    std::set<std::tuple<int64_t, int, int, int64_t, int>> bin_checked;
     // once a graph has been captured, scratch that it may reference is never freed early
     bool captured = false;
     std::vector<void*> retired;
@@ -171,7 +174,7 @@ int64_t total_records(const BatchDesc& bd) {
     return r;
 }
 
-constexpr int64_t kMaxBinBytes = (int64_t)4 << 30;    // largest tile-bin allocation
+constexpr int64_t kMaxBinBytes = (int64_t)32 << 30;   // largest tile-bin allocation
 
 // Grows the bin capacity when the largest bin of an earlier call (read back
 // asynchronously) did not fit; never while capturing.
@@ -198,54 +201,82 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     const int64_t C = (mesh->n_tris + kClusterTris - 1) / kClusterTris;
     const int64_t R = total_records(bd);
     adapt_bin_cap(ctx, R);
-    Carve cv;
-    const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P + 1 + 2 * R);   // vis_count, vis_tris, bin_max, bin fills
-    const size_t o_vis = cv.take<uint2>((int64_t)P * C);
-    const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
-    const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
-    const size_t o_bin = cv.take<uint32_t>(R * (int64_t)ctx->bin_cap);
-    int rc = ensure_scratch(ctx, cv.off);
-    if (rc) return rc;
-    int32_t* vis_count = at<int32_t>(ctx, o_cnt);
-    int32_t* vis_tris = vis_count + P;
-    int32_t* bin_max = vis_tris + P;
-    int32_t* bin_small = bin_max + 1;
-    int32_t* bin_big = bin_small + R;
-    const void* prep = mesh->clusters;
-    if (!prep && C > 0) {
-        void* w = at<char>(ctx, o_cb);
-        RM_HIP(ctx, launch_prepare(ctx->stream, mesh->xyz, mesh->n_vertices, mesh->tri, mesh->n_tris, w));
-        prep = w;
-    }
-    const ClusterBounds* cb = static_cast<const ClusterBounds*>(prep);
-    const float* nrm = prep ? reinterpret_cast<const float*>(static_cast<const char*>(prep) +
-                                                             prepared_normals_offset(mesh->n_tris))
-                            : nullptr;
-    RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P + 1 + 2 * R));
-    uint2* vis = at<uint2>(ctx, o_vis);
-    RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
+    // The first uncaptured call of a launch shape reads the largest bin fill
+    // back right after binning and, if the bins were too small, grows them and
+    // bins again, so that no call of that shape takes the slow every-cluster
+    // path of an overflowing bin; later calls adapt asynchronously.
+    const auto shape = std::make_tuple(R, tw, th, mesh->n_tris, P);
+    const bool check = !capturing(ctx) && ctx->bin_checked.count(shape) == 0;
     RasterArgs a;
-    a.xyz = mesh->xyz;
-    a.tri = mesh->tri;
-    a.cls = mesh->cls;
-    a.nrm = nrm;
-    a.n_tris = mesh->n_tris;
-    a.vmax = mesh->n_vertices > 0 ? (uint32_t)(mesh->n_vertices - 1) : 0u;
-    a.n_clusters = (int32_t)C;
-    a.T_wc = T_wc;
-    a.vis = vis;
-    a.vis_count = vis_count;
-    a.bins = at<uint32_t>(ctx, o_bin);
-    a.bin_small = bin_small;
-    a.bin_big = bin_big;
-    a.bin_max = bin_max;
-    a.bin_cap = ctx->bin_cap;
-    a.rec = at<float>(ctx, o_rec);
-    a.eps = eps;
-    a.depth_out = depth_out;
-    a.tri_out = tri_out;
-    a.cls_out = cls_out;
-    RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
+    int32_t* vis_count = nullptr;
+    int32_t* vis_tris = nullptr;
+    int32_t* bin_max = nullptr;
+    for (int attempt = 0;; ++attempt) {
+        // the capacity learned so far, limited to what this call's records may take
+        int64_t cap = ctx->bin_cap;
+        while (cap > 1024 && R * cap * 4 > kMaxBinBytes) cap /= 2;
+        Carve cv;
+        const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P + 3 + 2 * R);   // vis_count, vis_tris, bin_max, bin_fill[2], bin fills
+        const size_t o_vis = cv.take<uint2>((int64_t)P * C);
+        const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
+        const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
+        const size_t o_bin = cv.take<uint32_t>(R * cap);
+        int rc = ensure_scratch(ctx, cv.off);
+        if (rc) return rc;
+        vis_count = at<int32_t>(ctx, o_cnt);
+        vis_tris = vis_count + P;
+        bin_max = vis_tris + P;
+        int32_t* bin_fill = bin_max + 1;
+        int32_t* bin_small = bin_fill + 2;
+        int32_t* bin_big = bin_small + R;
+        const void* prep = mesh->clusters;
+        if (!prep && C > 0) {
+            void* w = at<char>(ctx, o_cb);
+            RM_HIP(ctx, launch_prepare(ctx->stream, mesh->xyz, mesh->n_vertices, mesh->tri, mesh->n_tris, w));
+            prep = w;
+        }
+        const ClusterBounds* cb = static_cast<const ClusterBounds*>(prep);
+        const float* nrm = prep ? reinterpret_cast<const float*>(static_cast<const char*>(prep) +
+                                                                 prepared_normals_offset(mesh->n_tris))
+                                : nullptr;
+        RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P + 3 + 2 * R));
+        uint2* vis = at<uint2>(ctx, o_vis);
+        RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
+        a.xyz = mesh->xyz;
+        a.tri = mesh->tri;
+        a.cls = mesh->cls;
+        a.nrm = nrm;
+        a.n_tris = mesh->n_tris;
+        a.vmax = mesh->n_vertices > 0 ? (uint32_t)(mesh->n_vertices - 1) : 0u;
+        a.n_clusters = (int32_t)C;
+        a.T_wc = T_wc;
+        a.vis = vis;
+        a.vis_count = vis_count;
+        a.bins = at<uint32_t>(ctx, o_bin);
+        a.bin_small = bin_small;
+        a.bin_big = bin_big;
+        a.bin_max = bin_max;
+        a.bin_fill = bin_fill;
+        a.bin_cap = (int32_t)cap;
+        a.rec = at<float>(ctx, o_rec);
+        a.eps = eps;
+        a.depth_out = depth_out;
+        a.tri_out = tri_out;
+        a.cls_out = cls_out;
+        RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
+        if (!check || attempt > 0) break;
+        RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 2, bin_fill, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->bin_checked.insert(shape);
+        const int64_t need = (int64_t)ctx->pinned[2] + (int64_t)ctx->pinned[3];
+        if (need <= cap) break;
+        int64_t grown = cap;
+        while (grown < need + need / 4 && grown < ((int64_t)1 << 24)) grown *= 2;
+        while (grown > 1024 && R * grown * 4 > kMaxBinBytes) grown /= 2;
+        if (grown <= cap) break;               // cannot grow: overflowing bins take the slow path
+        ctx->bin_cap = (int32_t)std::max<int64_t>(grown, ctx->bin_cap);
+    }
     hipEvent_t pe1 = nullptr;
     if (ctx->profiling && !capturing(ctx)) {
         if (ctx->prof_used == ctx->prof_events.size()) {

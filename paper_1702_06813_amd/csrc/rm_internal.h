@@ -64,6 +64,7 @@ struct RasterArgs {
     int32_t* bin_small;          // [n_records] small entries appended (may exceed bin_cap)
     int32_t* bin_big;            // [n_records] large entries appended
     int32_t* bin_max;            // device scalar: largest bin fill of the call
+    int32_t* bin_fill;           // device [2]: largest small and large fill reserved by the binning pass
     int32_t bin_cap;
     float* rec;                  // partial records [n_records][kRecFields]
     float eps;

@@ -639,8 +639,14 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
             const uint32_t n = tcnt[i];
             if (n) {
                 const int tile = (ry0 + i / rw) * sd.tiles_x + rx0 + i % rw;
-                if (n & 0xffffu) tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
-                if (n >> 16) tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
+                if (n & 0xffffu) {
+                    tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
+                    atomicMax(a.bin_fill, (int)(tbs[i] + (n & 0xffffu)));
+                }
+                if (n >> 16) {
+                    tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
+                    atomicMax(a.bin_fill + 1, (int)(tbb[i] + (n >> 16)));
+                }
                 tcnt[i] = 0;
             }
         }

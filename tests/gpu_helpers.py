@@ -42,6 +42,23 @@ def oracle_map(name: str):
     return np.concatenate(xyz), np.concatenate(tri).astype(np.int32), np.concatenate(cls)
 
 
+@functools.lru_cache(maxsize=None)
+def stream(name: str):
+    return getattr(configs, name)()
+
+
+@functools.lru_cache(maxsize=None)
+def stream_map(name: str):
+    """Map mesh of a multi-scan stream: the oracle's meshification of every view."""
+    st = stream(name)
+    parts = [O.meshify(d, st.view_cam, T, st.stride, st.z_min, st.z_max, st.max_edge, st.smooth_radius)
+             for T, d in zip(st.views, st.view_depths)]
+    xyz, tri, cls, off = [], [], [], 0
+    for v, t, c in parts:
+        xyz.append(v); tri.append(t + off); cls.append(c); off += len(v)
+    return np.concatenate(xyz), np.concatenate(tri).astype(np.int32), np.concatenate(cls)
+
+
 def sample_pixels(cam, n, seed):
     rng = np.random.default_rng(seed)
     N = cam.width * cam.height

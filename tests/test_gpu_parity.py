@@ -2,9 +2,11 @@
 
 Every input is seeded and synthetic; every expected value comes from the
 oracle.  Sizes: the tiny room at full frame (several tiles plus ragged
-edges), the Kinect-like map at 640x480 on sampled pixels, and the 1M-triangle
-differentiation map at the launch configuration the benchmark times, on
-sampled pixels.
+edges), the Kinect-like map at 640x480 on sampled pixels, the 1M-triangle
+differentiation map at the launch configuration the benchmark times, the
+~4M-triangle wide-FOV corridor at 1280x960 with 256 poses per launch, and the
+uneven stream of 32 scans of three resolutions against a 2.1M-triangle map,
+on sampled pixels.
 """
 import sys
 
@@ -14,7 +16,8 @@ import pytest
 from oracle import oracle as O
 from workloads import scenes as S
 
-from gpu_helpers import EPS, compare_records, flagged_pixels, oracle_map, render_mismatch, sample_pixels, workload
+from gpu_helpers import (EPS, compare_records, flagged_pixels, oracle_map, render_mismatch, sample_pixels, stream,
+                         stream_map, workload)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -182,24 +185,31 @@ def test_render_empty_mesh_and_pointing_away(rm):
 def _cost_case(rm, name, poses, pixels, grad=True, mesh_np=None):
     w = workload(name)
     mesh_np = oracle_map(name) if mesh_np is None else mesh_np
-    d, c = O.scan_image(w.scan_depth, w.z_min, w.z_max)
-    dm = _dev_mesh(rm, mesh_np)
-    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), w.z_min, w.z_max, cam=w.cam)
+    return _cost_case_scan(rm, mesh_np, w.cam, w.scan_depth, w.z_min, w.z_max, poses, pixels, grad)
+
+
+def _cost_case_scan(rm, mesh_np, cam, scan_depth, z_min, z_max, poses, pixels, grad=True, dm=None):
+    """GPU records of single-pose launches restricted (by the scan mask) to
+    the sampled pixels the oracle does not flag, against the oracle's
+    reduction over the same pixels."""
+    d, c = O.scan_image(scan_depth, z_min, z_max)
+    dm = _dev_mesh(rm, mesh_np) if dm is None else dm
+    scan = rm.scan_image(torch.from_numpy(scan_depth).to(DEV), z_min, z_max, cam=cam)
     res = []
     masks = []
     for b, T in enumerate(poses):
-        rend = O.render(mesh_np, w.cam, T, pixels)
-        terms = O.pixel_terms(rend, mesh_np[2], d, c, w.cam, EPS)
-        flagged = flagged_pixels(rend, terms, w.cam, EPS)
+        rend = O.render(mesh_np, cam, T, pixels)
+        terms = O.pixel_terms(rend, mesh_np[2], d, c, cam, EPS)
+        flagged = flagged_pixels(rend, terms, cam, EPS)
         keep = ~flagged
         ref = O.reduce_terms(terms, keep)
-        mask = np.zeros(w.cam.width * w.cam.height, np.uint8)
+        mask = np.zeros(cam.width * cam.height, np.uint8)
         mask[rend["pixels"][keep]] = 1
         masks.append(mask)
         res.append((ref, terms, keep))
     outs = []
     for b, T in enumerate(poses):
-        scan.mask = torch.from_numpy(masks[b].reshape(w.cam.height, w.cam.width)).to(DEV)
+        scan.mask = torch.from_numpy(masks[b].reshape(cam.height, cam.width)).to(DEV)
         f = rm.align_cost_grad if grad else rm.align_cost
         outs.append(f(dm, scan, _T([T]), EPS).cpu().numpy()[0])
     for b in range(len(poses)):
@@ -231,6 +241,49 @@ def test_cost_grad_differentiation_1m_sampled(rm):
     _say("cost differentiation (1M triangles)")
     w = workload("differentiation")
     _cost_case(rm, "differentiation", list(w.poses[:2]), sample_pixels(w.cam, 1500, 13))
+
+
+@pytest.mark.slow
+def test_cost_grad_wide_4m_full_batch(rm):
+    """Wide-FOV corridor: 1280x960, ~4M triangles, 10% dead pixels, 256 poses
+    in one launch.  Rows of the full launch equal single-pose launches, and
+    sampled pixels of two poses match the oracle."""
+    _say("cost wide (4M triangles, 256 poses)")
+    w = workload("wide")
+    mesh = oracle_map("wide")
+    dm = _dev_mesh(rm, mesh)
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), w.z_min, w.z_max, cam=w.cam)
+    T = _T(w.poses)
+    allr = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
+    assert allr.shape[0] == 256
+    for i in (0, 131, 255):
+        one = rm.align_cost_grad(dm, scan, T[i:i + 1].contiguous(), EPS).cpu().numpy()
+        np.testing.assert_array_equal(one[0], allr[i])
+    _cost_case_scan(rm, mesh, w.cam, w.scan_depth, w.z_min, w.z_max, list(w.poses[:2]),
+                    sample_pixels(w.cam, 800, 14), dm=dm)
+
+
+@pytest.mark.slow
+def test_uneven_stream_full_shape(rm):
+    """32 scans of 320x240, 640x480 and 1280x960 with 16-128 poses each in one
+    launch against the 2.1M-triangle corridor map: rows equal one launch per
+    scan, and sampled pixels of one pose per resolution match the oracle."""
+    _say("uneven stream (32 scans, 2.1M triangles)")
+    st = stream("uneven")
+    mesh = stream_map("uneven")
+    dm = _dev_mesh(rm, mesh)
+    scans = [rm.scan_image(torch.from_numpy(s.depth).to(DEV), st.z_min, st.z_max, cam=s.cam) for s in st.scans]
+    counts = [len(s.poses) for s in st.scans]
+    T = _T(np.concatenate([s.poses for s in st.scans]))
+    allr = rm.align_cost_grad(dm, scans, T, EPS, poses_per_scan=counts).cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for k in (0, 1, 2, 31):
+        sep = rm.align_cost_grad(dm, scans[k], T[off[k]:off[k + 1]].contiguous(), EPS).cpu().numpy()
+        np.testing.assert_array_equal(sep, allr[off[k]:off[k + 1]])
+    for k in (0, 1, 2):
+        s = st.scans[k]
+        _cost_case_scan(rm, mesh, s.cam, s.depth, st.z_min, st.z_max, [s.poses[0]],
+                        sample_pixels(s.cam, 600, 20 + k), dm=dm)
 
 
 def test_unmasked_totals_within_flag_bound(rm):

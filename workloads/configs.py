@@ -110,3 +110,57 @@ def wide(seed: int = 4, n_poses: int = 256, cell=0.018) -> Workload:
     depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.01, dead=0.10)
     poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n_poses)])
     return Workload("wide", cam, scene, T, depth, poses, map_mesh=mesh)
+
+
+@dataclass
+class StreamScan:
+    cam: S.Camera
+    T_true: np.ndarray                 # [3,4] ground truth of the scan
+    depth: np.ndarray                  # [H,W] f32 range image
+    poses: np.ndarray                  # [n,3,4] candidate poses
+
+
+@dataclass
+class Stream:
+    """Several scans of different resolutions, each with its own candidate
+    poses, scored against one map in a single launch."""
+    name: str
+    scene: S.Scene
+    view_cam: S.Camera
+    views: list
+    view_depths: list
+    scans: list
+    stride: int = 2
+    max_edge: float = 0.1
+    smooth_radius: int = 2
+    z_min: float = 0.5
+    z_max: float = 8.0
+
+
+def _corridor_pose(x, phase=0.0):
+    """Sensor on a walk down the corridor: weaving across it, bobbing, yawing
+    about the axis and tilted slightly down."""
+    pos = np.array([x, 1.25 + 0.3 * np.sin(x / 3.0 + phase), 1.4 + 0.1 * np.sin(x / 5.0)])
+    return S.look_pose(pos, 0.25 * np.sin(x / 4.0 + phase), -0.1)
+
+
+def uneven(seed: int = 5, n_views: int = 56, n_scans: int = 32) -> Stream:
+    """60 m cluttered corridor; map = 56 QVGA views 1 m apart along the walk,
+    meshified at stride 2 with smoothing radius 2 (56 x 37,842 = 2,119,152
+    triangles); 32 query scans between the views, cycling 320x240, 640x480 and
+    1280x960, each with 16-128 candidates N(0, 3 cm) / N(0, 1.5 deg)."""
+    scene = S.corridor_scene(seed)
+    views = [_corridor_pose(1.0 + k) for k in range(n_views)]
+    depths = [S.range_image(scene, S.QVGA, T, seed * 1000 + k, noise_rel=0.01, dropout=0.02)
+              for k, T in enumerate(views)]
+    rng = np.random.default_rng(seed)
+    cams = (S.QVGA, S.KINECT, S.WIDE)
+    scans = []
+    for j in range(n_scans):
+        T = _corridor_pose(1.37 + j * 1.7, phase=0.2)
+        cam = cams[j % 3]
+        depth = S.range_image(scene, cam, T, seed * 100 + j, noise_rel=0.01, dropout=0.02)
+        n = int(rng.integers(16, 129))
+        poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n)])
+        scans.append(StreamScan(cam, T, depth, poses))
+    return Stream("uneven", scene, S.QVGA, views, depths, scans)

@@ -192,9 +192,11 @@ def _rays(cam: Camera, T: np.ndarray):
     return rw, T[:, 3]
 
 
-def analytic_depth(scene: Scene, cam: Camera, T: np.ndarray) -> np.ndarray:
+def analytic_depth(scene: Scene, cam: Camera, T: np.ndarray, z_cut=np.inf) -> np.ndarray:
     """Exact (FP64) z-depth of the first surface hit for every pixel; +inf
-    where the ray leaves through a door opening."""
+    where the ray leaves through a door opening.  Boxes entirely behind the
+    camera or entirely beyond depth ``z_cut`` are skipped: their hits could
+    only lie beyond z_cut (callers treat such depths alike)."""
     rw, o = _rays(cam, T)
     with np.errstate(divide="ignore", invalid="ignore"):
         inv = 1.0 / rw
@@ -214,6 +216,11 @@ def analytic_depth(scene: Scene, cam: Camera, T: np.ndarray) -> np.ndarray:
                           (p[..., 2] >= d.lo[1]) & (p[..., 2] <= d.hi[1]))
                 depth = np.where(on_wall & inside, np.inf, depth)
         for lo, hi in scene.boxes:
+            corners = np.array([[lo[0] if i & 1 else hi[0], lo[1] if i & 2 else hi[1], lo[2] if i & 4 else hi[2]]
+                                for i in range(8)])
+            zc = (corners - o) @ T[:, 2]
+            if zc.max() <= 0.0 or zc.min() > z_cut:
+                continue
             t1 = (lo - o) * inv
             t2 = (hi - o) * inv
             tn = np.nanmax(np.minimum(t1, t2), axis=-1)
@@ -230,7 +237,7 @@ def range_image(scene: Scene, cam: Camera, T: np.ndarray, seed: int, noise_rel=0
     ``dropout`` of pixels forced to no return and a fraction ``dead`` to NaN.
     Returns float32 [H, W]."""
     rng = np.random.default_rng(seed)
-    z = analytic_depth(scene, cam, T)
+    z = analytic_depth(scene, cam, T, z_cut=z_max)
     if noise_rel:
         z = z * (1.0 + noise_rel * rng.standard_normal(z.shape))
     z = np.where(np.isfinite(z) & (z <= z_max), z, 0.0)
