@@ -156,6 +156,17 @@ const char* rm_last_error(const rm_ctx* ctx);
  * 16x16, 32x32, 64x32; (0, 0) restores automatic choice (autotuned when
  * rm_autotune is on, 64x32 otherwise).  Results do not depend on it. */
 int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
+/* Work scheduling of the rasterizer over (scan, pose, tile) items:
+ *   0  automatic: currently 2, measured faster for single- and multi-scan
+ *      batches alike
+ *   1  one workgroup per item, items in an XCD-aware order (neighbouring
+ *      poses of a tile on one XCD, sharing its L2)
+ *   2  persistent: after binning, items are ordered longest first (counting
+ *      sort by log2 of their bin fill) and as many workgroups as fit on the
+ *      device take the next item from a queue until it is empty
+ * Results do not depend on it (each item writes its own partial record).
+ * Returns RM_ERR_INVALID_ARG for other values. */
+int rm_set_schedule(rm_ctx* ctx, int32_t mode);
 /* Turns the tile autotuner on or off.  When on, the first call for a new
  * (image size, pose count, triangle count) times the tile shapes on the
  * call's own inputs, largest first, stopping at the first shape more than

@@ -26,6 +26,7 @@ struct rm_ctx {
     int32_t* pinned = nullptr;        // small host readback buffer
     std::string err;
     int tile_w = 0, tile_h = 0;       // 0 = automatic
+    int schedule = 0;                 // 0 automatic (= 2), 1 one workgroup per item, 2 persistent longest-first
     bool autotune = false;
     std::map<std::tuple<int, int, int, int64_t, int>, std::pair<int, int>> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -207,6 +208,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     // path of an overflowing bin; later calls adapt asynchronously.
     const auto shape = std::make_tuple(R, tw, th, mesh->n_tris, P);
     const bool check = !capturing(ctx) && ctx->bin_checked.count(shape) == 0;
+    const bool persistent = ctx->schedule != 1;
     RasterArgs a;
     int32_t* vis_count = nullptr;
     int32_t* vis_tris = nullptr;
@@ -216,7 +218,10 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         int64_t cap = ctx->bin_cap;
         while (cap > 1024 && R * cap * 4 > kMaxBinBytes) cap /= 2;
         Carve cv;
-        const size_t o_cnt = cv.take<int32_t>(2 * (int64_t)P + 3 + 2 * R);   // vis_count, vis_tris, bin_max, bin_fill[2], bin fills
+        // vis_count, vis_tris, bin_max, bin_fill[2], bin fills, order histogram and cursors, queue
+        const int64_t n_cnt = 2 * (int64_t)P + 3 + 2 * R + 65;
+        const size_t o_cnt = cv.take<int32_t>(n_cnt);
+        const size_t o_ord = cv.take<int32_t>(persistent ? R : 1);
         const size_t o_vis = cv.take<uint2>((int64_t)P * C);
         const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
         const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
@@ -229,6 +234,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         int32_t* bin_fill = bin_max + 1;
         int32_t* bin_small = bin_fill + 2;
         int32_t* bin_big = bin_small + R;
+        int32_t* hist = bin_big + R;
         const void* prep = mesh->clusters;
         if (!prep && C > 0) {
             void* w = at<char>(ctx, o_cb);
@@ -239,7 +245,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         const float* nrm = prep ? reinterpret_cast<const float*>(static_cast<const char*>(prep) +
                                                                  prepared_normals_offset(mesh->n_tris))
                                 : nullptr;
-        RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, 2 * (int64_t)P + 3 + 2 * R));
+        RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, n_cnt));
         uint2* vis = at<uint2>(ctx, o_vis);
         RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
         a.xyz = mesh->xyz;
@@ -258,12 +264,20 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.bin_max = bin_max;
         a.bin_fill = bin_fill;
         a.bin_cap = (int32_t)cap;
+        a.order = nullptr;
+        a.queue = hist + 64;
+        a.n_order = (int32_t)R;
         a.rec = at<float>(ctx, o_rec);
         a.eps = eps;
         a.depth_out = depth_out;
         a.tri_out = tri_out;
         a.cls_out = cls_out;
         RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
+        if (persistent) {
+            int32_t* order = at<int32_t>(ctx, o_ord);
+            RM_HIP(ctx, launch_order(ctx->stream, bin_small, bin_big, R, hist, order));
+            a.order = order;
+        }
         if (!check || attempt > 0) break;
         RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 2, bin_fill, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -446,6 +460,14 @@ int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h) {
     if (!valid_tile(tile_w, tile_h)) return fail(ctx, RM_ERR_INVALID_ARG, "tile %dx%d not supported", tile_w, tile_h);
     ctx->tile_w = tile_w;
     ctx->tile_h = tile_h;
+    return RM_OK;
+}
+
+int rm_set_schedule(rm_ctx* ctx, int32_t mode) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (mode < 0 || mode > 2) return fail(ctx, RM_ERR_INVALID_ARG, "schedule %d outside 0..2", mode);
+    ctx->schedule = mode;
     return RM_OK;
 }
 

@@ -66,6 +66,9 @@ struct RasterArgs {
     int32_t* bin_max;            // device scalar: largest bin fill of the call
     int32_t* bin_fill;           // device [2]: largest small and large fill reserved by the binning pass
     int32_t bin_cap;
+    const int32_t* order;        // null: one workgroup per item; else record indices, longest first
+    int32_t* queue;              // device counter of taken items (persistent scheduling)
+    int32_t n_order;
     float* rec;                  // partial records [n_records][kRecFields]
     float eps;
     // render outputs
@@ -92,6 +95,12 @@ hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds*
                        int32_t* vis_tris);
 hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a);
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode);
+// Longest-first order of the records of a binned call: counting sort of the
+// records by log2 of their bin fill, descending.  hist: 32 zeroed counters.
+hipError_t launch_order(hipStream_t st, const int32_t* bin_small, const int32_t* bin_big, int64_t n_records,
+                        int32_t* hist, int32_t* order);
+// Workgroups of the persistent rasterizer that fit on the device at once.
+int persistent_grid(int tile_w, int tile_h, int mode);
 hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec,
                          const int32_t* vis_tris, float eps, int grad, double* out);
 hipError_t launch_gn_step(hipStream_t st, const double* out, int32_t P, double lambda, double* T,

@@ -724,14 +724,24 @@ __device__ __forceinline__ bool decode_item(const BatchDesc& bd, ItemInfo& it) {
     return true;
 }
 
-template <int TW, int TH, int MODE>
-__global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
-    __shared__ uint64_t keys[TW * TH];
-    __shared__ Queues q;
-    __shared__ float red[kWG / 64][kRecFields];
+// Item of a partial-record index (persistent scheduling takes items by record).
+__device__ __forceinline__ void decode_rec(const BatchDesc& bd, int64_t rec, ItemInfo& it) {
+    int s = 0;
+    while (s + 1 < bd.n_scans && rec >= bd.s[s + 1].rec_off) ++s;
+    const ScanDesc& sd = bd.s[s];
+    const int64_t local = rec - sd.rec_off;
+    const int nt = sd.tiles_x * sd.tiles_y;
+    it.scan = s;
+    it.pose_local = (int)(local / nt);
+    it.tile = (int)(local % nt);
+    it.pose = sd.pose_off + it.pose_local;
+    it.rec = rec;
+}
 
-    ItemInfo it;
-    if (!decode_item(bd, it)) return;
+// One (scan, pose, tile) item: rasterization rounds, resolve, tile record.
+template <int TW, int TH, int MODE>
+__device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs& a, const ItemInfo& it,
+                                          uint64_t* keys, Queues& q, float (*red)[kRecFields]) {
     const ScanDesc& sd = bd.s[it.scan];
     CamF cam{sd.fx, sd.fy, sd.cx, sd.cy, sd.z_near, sd.z_far, sd.width, sd.height};
     const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
@@ -938,6 +948,34 @@ __global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
     }
 }
 
+// Either one workgroup per item in the XCD-aware order, or, with an item
+// order, persistent workgroups that take the next item of the order (longest
+// first) from a global counter until it runs past the end; every workgroup
+// reaches that exit.
+template <int TW, int TH, int MODE>
+__global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
+    __shared__ uint64_t keys[TW * TH];
+    __shared__ Queues q;
+    __shared__ float red[kWG / 64][kRecFields];
+    if (!a.order) {
+        ItemInfo it;
+        if (!decode_item(bd, it)) return;
+        tile_pass<TW, TH, MODE>(bd, a, it, keys, q, red);
+        return;
+    }
+    __shared__ int slot;
+    for (;;) {
+        __syncthreads();                       // the previous item's shared data is no longer read
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int k = slot;
+        if (k >= a.n_order) return;
+        ItemInfo it;
+        decode_rec(bd, a.order[k], it);
+        tile_pass<TW, TH, MODE>(bd, a, it, keys, q, red);
+    }
+}
+
 // ------------------------------------------------------------------ cluster cull
 
 __device__ __forceinline__ void proj_acc(double fx, double fy, double cx, double cy, double x, double y,
@@ -1089,10 +1127,61 @@ hipError_t launch_bin_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ longest-first order
+
+constexpr int kOrderBuckets = 32;
+
+// bucket 0 holds the costliest records: 31 - floor(log2(fill + 1))
+__device__ __forceinline__ int order_bucket(const int32_t* bs, const int32_t* bb, int64_t r) {
+    const uint32_t c = (uint32_t)bs[r] + (uint32_t)bb[r] + 1u;
+    return __clz(c);
+}
+
+__global__ void __launch_bounds__(kWG) k_order_count(const int32_t* __restrict__ bs, const int32_t* __restrict__ bb,
+                                                     int64_t n, int32_t* __restrict__ hist) {
+    __shared__ int h[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (r < n) atomicAdd(&h[order_bucket(bs, bb, r)], 1);
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// hist[0..31] counts -> hist[32..63] running cursors (exclusive prefix)
+__global__ void k_order_offsets(int32_t* hist) {
+    if (threadIdx.x != 0) return;
+    int acc = 0;
+    for (int k = 0; k < kOrderBuckets; ++k) {
+        hist[kOrderBuckets + k] = acc;
+        acc += hist[k];
+    }
+}
+
+__global__ void __launch_bounds__(kWG) k_order_scatter(const int32_t* __restrict__ bs, const int32_t* __restrict__ bb,
+                                                       int64_t n, int32_t* __restrict__ hist,
+                                                       int32_t* __restrict__ order) {
+    __shared__ int h[kOrderBuckets], base[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int b = r < n ? order_bucket(bs, bb, r) : 0;
+    if (r < n) atomicAdd(&h[b], 1);
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets) {
+        const int c = h[threadIdx.x];
+        base[threadIdx.x] = c ? atomicAdd(&hist[kOrderBuckets + threadIdx.x], c) : 0;
+        h[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    if (r < n) order[base[b] + atomicAdd(&h[b], 1)] = (int32_t)r;
+}
+
 template <int TW, int TH>
 hipError_t launch_raster_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {
     const int64_t chunk = (bd.n_items + 7) / 8;
-    const dim3 grid((unsigned)(chunk * 8));
+    const dim3 grid(a.order ? (unsigned)std::min<int64_t>(persistent_grid(TW, TH, mode), a.n_order)
+                            : (unsigned)(chunk * 8));
     if (mode == kRender) hipLaunchKernelGGL((k_raster<TW, TH, kRender>), grid, dim3(kWG), 0, st, bd, a);
     else if (mode == kCost) hipLaunchKernelGGL((k_raster<TW, TH, kCost>), grid, dim3(kWG), 0, st, bd, a);
     else hipLaunchKernelGGL((k_raster<TW, TH, kGrad>), grid, dim3(kWG), 0, st, bd, a);
@@ -1114,6 +1203,45 @@ hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) 
     if (bd.tile_w == 16 && bd.tile_h == 16) return launch_bin_t<16, 16>(st, bd, a);
     if (bd.tile_w == 64 && bd.tile_h == 32) return launch_bin_t<64, 32>(st, bd, a);
     return launch_bin_t<32, 32>(st, bd, a);
+}
+
+hipError_t launch_order(hipStream_t st, const int32_t* bin_small, const int32_t* bin_big, int64_t n_records,
+                        int32_t* hist, int32_t* order) {
+    if (n_records <= 0) return hipSuccess;
+    const unsigned g = (unsigned)((n_records + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_order_count, dim3(g), dim3(kWG), 0, st, bin_small, bin_big, n_records, hist);
+    hipLaunchKernelGGL(k_order_offsets, dim3(1), dim3(64), 0, st, hist);
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(kWG), 0, st, bin_small, bin_big, n_records, hist, order);
+    return hipGetLastError();
+}
+
+namespace {
+template <int TW, int TH, int MODE>
+int resident_blocks() {
+    static int cached = 0;
+    if (!cached) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster<TW, TH, MODE>, kWG, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 1024;
+        }
+        cached = std::max(1, per_cu) * std::max(1, cus);
+    }
+    return cached;
+}
+template <int TW, int TH>
+int resident_t(int mode) {
+    return mode == kRender ? resident_blocks<TW, TH, kRender>()
+                           : (mode == kCost ? resident_blocks<TW, TH, kCost>() : resident_blocks<TW, TH, kGrad>());
+}
+}  // namespace
+
+int persistent_grid(int tile_w, int tile_h, int mode) {
+    if (tile_w == 16 && tile_h == 16) return resident_t<16, 16>(mode);
+    if (tile_w == 64 && tile_h == 32) return resident_t<64, 32>(mode);
+    return resident_t<32, 32>(mode);
 }
 
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {

@@ -26,7 +26,7 @@ CLUSTER_TRIS = 256
 
 ABI_SYMBOLS = [
     "rm_ctx_create", "rm_ctx_destroy", "rm_ctx_set_stream", "rm_last_error", "rm_set_tile", "rm_autotune",
-    "rm_get_tile", "rm_profile", "rm_profile_read", "rm_graph_begin", "rm_graph_end", "rm_graph_launch", "rm_graph_destroy", "rm_scan_image",
+    "rm_get_tile", "rm_set_schedule", "rm_profile", "rm_profile_read", "rm_graph_begin", "rm_graph_end", "rm_graph_launch", "rm_graph_destroy", "rm_scan_image",
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
     "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract",
 ]
@@ -78,6 +78,7 @@ def load_library(path: Path | str | None = None):
             "rm_ctx_set_stream": [V, V],
             "rm_set_tile": [V, I32, I32],
             "rm_autotune": [V, I32],
+            "rm_set_schedule": [V, I32],
             "rm_get_tile": [V, I32, I32, I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)],
             "rm_profile": [V, I32],
             "rm_profile_read": [V, ctypes.POINTER(I64), ctypes.POINTER(D)],
@@ -140,6 +141,10 @@ class Context:
     def set_tile(self, w: int, h: int):
         _check(self.lib.rm_set_tile(self.handle, w, h), self.handle)
 
+    def set_schedule(self, mode: int):
+        """rm_set_schedule: 0 automatic (persistent), 1 one workgroup per item, 2 persistent longest-first."""
+        self.call("rm_set_schedule", int(mode))
+
     def autotune(self, enable: bool = True):
         _check(self.lib.rm_autotune(self.handle, int(enable)), self.handle)
 
@@ -164,7 +169,9 @@ class Context:
 _ctxs: dict[int, Context] = {}
 
 
-def context(device: int | torch.device | None = None) -> Context:
+def context(device: int | str | torch.device | None = None) -> Context:
+    if isinstance(device, str):
+        device = torch.device(device)
     if device is None:
         idx = torch.cuda.current_device()
     elif isinstance(device, torch.device):

@@ -381,6 +381,46 @@ def test_multi_scan_uneven_batch(rm):
     assert abs(allr[-1][0] - ref["e_table"]) <= 2 * flagged_pixels(ref["render"], ref["terms"], S.TINY, EPS).sum()
 
 
+def test_schedules_give_identical_records(rm):
+    """One workgroup per item, persistent longest-first and automatic
+    scheduling give bit-identical records, for one scan and for an uneven
+    multi-scan batch; a captured persistent launch replays identically."""
+    _say("schedules")
+    wk = workload("kinect")
+    dm = _dev_mesh(rm, oracle_map("kinect"))
+    scan = rm.scan_image(torch.from_numpy(wk.scan_depth).to(DEV), cam=wk.cam)
+    T = _T(wk.poses[:24])
+    cams = [S.QVGA, S.KINECT, S.Camera(400.0, 400.0, 249.5, 149.5, 500, 300)]
+    scans = [rm.scan_image(torch.from_numpy(S.range_image(wk.scene, c, wk.T_true, 60 + k, dropout=0.02)).to(DEV),
+                           cam=c) for k, c in enumerate(cams)]
+    counts = [7, 13, 4]
+    ctx = rm.context()
+    res = {}
+    try:
+        for mode in (1, 2, 0):
+            ctx.set_schedule(mode)
+            one = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
+            multi = rm.align_cost_grad(dm, scans, T, EPS, poses_per_scan=counts).cpu().numpy()
+            res[mode] = (one, multi)
+        for mode in (2, 0):
+            np.testing.assert_array_equal(res[mode][0], res[1][0])
+            np.testing.assert_array_equal(res[mode][1], res[1][1])
+        ctx.set_schedule(2)
+        out = torch.empty((24, rm.OUT_STRIDE), dtype=torch.float64, device=DEV)
+        rm.align_cost_grad(dm, scans, T, EPS, poses_per_scan=counts, out=out)
+        torch.cuda.synchronize()
+        g = rm.Graph(DEV)
+        with g:
+            rm.align_cost_grad(dm, scans, T, EPS, poses_per_scan=counts, out=out)
+        for _ in range(3):
+            out.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), res[1][1])
+    finally:
+        ctx.set_schedule(0)
+
+
 # ------------------------------------------------------------------ optimizer step, autograd, graphs
 
 def test_gn_step_and_retract_match_oracle(rm):
