@@ -262,7 +262,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.bin_small = bin_small;
         a.bin_big = bin_big;
         a.bin_max = bin_max;
-        a.bin_fill = bin_fill;
+        a.bin_fill = check && attempt == 0 ? bin_fill : nullptr;
         a.bin_cap = (int32_t)cap;
         a.order = nullptr;
         a.queue = hist + 64;

@@ -64,7 +64,7 @@ struct RasterArgs {
     int32_t* bin_small;          // [n_records] small entries appended (may exceed bin_cap)
     int32_t* bin_big;            // [n_records] large entries appended
     int32_t* bin_max;            // device scalar: largest bin fill of the call
-    int32_t* bin_fill;           // device [2]: largest small and large fill reserved by the binning pass
+    int32_t* bin_fill;           // device [2] or null: largest small and large fill reserved by the binning pass
     int32_t bin_cap;
     const int32_t* order;        // null: one workgroup per item; else record indices, longest first
     int32_t* queue;              // device counter of taken items (persistent scheduling)

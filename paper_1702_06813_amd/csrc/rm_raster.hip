@@ -635,19 +635,31 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
             if (h) atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], inc);
         }
         __syncthreads();
+        int fs = 0, fb = 0;                    // largest fills this thread reserved
         for (int i = threadIdx.x; i < nrect; i += kWG) {
             const uint32_t n = tcnt[i];
             if (n) {
                 const int tile = (ry0 + i / rw) * sd.tiles_x + rx0 + i % rw;
                 if (n & 0xffffu) {
                     tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
-                    atomicMax(a.bin_fill, (int)(tbs[i] + (n & 0xffffu)));
+                    fs = max(fs, (int)(tbs[i] + (n & 0xffffu)));
                 }
                 if (n >> 16) {
                     tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
-                    atomicMax(a.bin_fill + 1, (int)(tbb[i] + (n >> 16)));
+                    fb = max(fb, (int)(tbb[i] + (n >> 16)));
                 }
                 tcnt[i] = 0;
+            }
+        }
+        if (a.bin_fill) {                      // only when the host sizes the bins of a new shape
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                fs = max(fs, __shfl_xor(fs, off));
+                fb = max(fb, __shfl_xor(fb, off));
+            }
+            if ((threadIdx.x & 63) == 0 && (fs | fb)) {
+                atomicMax(a.bin_fill, fs);
+                atomicMax(a.bin_fill + 1, fb);
             }
         }
         __syncthreads();
