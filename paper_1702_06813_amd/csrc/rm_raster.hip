@@ -627,12 +627,18 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
         }
         const uint32_t inc = big ? 0x10000u : 1u;
         __syncthreads();
-        for (int i = 0; i < nspan; ++i) {
-            const int tx = tx0 + i % sw, ty = ty0 + i / sw;
-            const bool h = nspan <= 64 ? ((hits >> i) & 1) != 0
-                                       : (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1),
-                                                                   (float)(ty * TH), (float)(ty * TH + TH - 1)));
-            if (h) atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], inc);
+        if (nspan <= 64) {
+            for (uint64_t m = hits; m; m &= m - 1) {      // only the tiles hit
+                const int i = __ffsll((unsigned long long)m) - 1;
+                atomicAdd(&tcnt[(ty0 + i / sw - ry0) * rw + (tx0 + i % sw - rx0)], inc);
+            }
+        } else {
+            for (int i = 0; i < nspan; ++i) {
+                const int tx = tx0 + i % sw, ty = ty0 + i / sw;
+                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
+                                             (float)(ty * TH + TH - 1)))
+                    atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], inc);
+            }
         }
         __syncthreads();
         int fs = 0, fb = 0;                    // largest fills this thread reserved
@@ -663,12 +669,17 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
             }
         }
         __syncthreads();
-        for (int i = 0; i < nspan; ++i) {
+        uint64_t m = hits;
+        for (int i = 0; nspan <= 64 ? m != 0 : i < nspan; ++i) {
+            if (nspan <= 64) {                              // only the tiles hit
+                i = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+            }
             const int tx = tx0 + i % sw, ty = ty0 + i / sw;
-            const bool h = nspan <= 64 ? ((hits >> i) & 1) != 0
-                                       : (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1),
-                                                                   (float)(ty * TH), (float)(ty * TH + TH - 1)));
-            if (!h) continue;
+            if (nspan > 64 && test_tiles &&
+                !foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
+                           (float)(ty * TH + TH - 1)))
+                continue;
             const int li = (ty - ry0) * rw + (tx - rx0);
             const uint32_t old = atomicAdd(&tcnt[li], inc);
             uint32_t* bin = a.bins + (rec0 + ty * sd.tiles_x + tx) * (int64_t)cap;
