@@ -167,12 +167,15 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
 // its rows between the three edge crossings (FP64, exact to far below a
 // pixel) and gives only pixel centres inside it the exact int64 edge test.
 constexpr int kQCap = kWG + 32;            // queued sub-triangles per round (more go in-thread)
-constexpr int kBand = 4;                   // rows per job
-constexpr int kSmallArea = 32;             // bounding-box pixels rasterized by the owning thread
+constexpr int kBand = 2;                   // rows per job
+constexpr int kSmallArea = 64;             // bounding-box pixels rasterized by the owning thread
 constexpr int kFatPixels = 256;            // estimated covered pixels that send a triangle to the fat path
 constexpr int kFatCap = 32;
 
-constexpr int kMaxBands = 8;              // tile height / kBand for the tallest tile (32 rows)
+constexpr int kMaxBands = 16;             // tile height / kBand for the tallest tile (32 rows)
+static_assert(32 / kBand <= kMaxBands && kMaxBands <= 16, "job records hold a 4-bit band index");
+static_assert((kQCap << 4) + 15 <= 0xffff, "job records are 16-bit");
+static_assert(kSmallArea <= 64, "in-thread edge functions stay within int32 only for spans below 64 px");
 struct BigQueue {
     int X[3][kQCap], Y[3][kQCap];          // snapped vertices relative to the tile origin (1/256 px)
     double m[3][kQCap];                    // edge slope dx/dy (0 for horizontal edges)
