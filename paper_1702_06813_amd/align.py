@@ -11,6 +11,8 @@ plain_align    -- the paper's optimizer for its own cost (Sec. IV-C): a
                   differences), Nelder-Mead iterations and coordinate descent
                   near the minimum, minimizing E(X) of Table I with one render
                   (one rm_align_cost launch for a single pose) per evaluation.
+batched_plain_align -- the same optimizer for many alignments in lockstep,
+                  one launch per round of evaluations over all of them.
 
 Pose increments x = (upsilon, omega) are applied on the right, T exp(x).
 """
@@ -89,13 +91,20 @@ def batched_align(mesh, scans, T0, iters=20, eps=(0.5, 0.1), method="gn", lam=1e
 
 
 # ---------------------------------------------------------------------------- derivative-free (the paper's)
+#
+# The optimizers are generators: each yields the next point it needs and is
+# sent that point's cost, and returns (x, fx, evaluations).  One generator
+# driven by a function is the plain form; many driven together share one
+# batched launch per round of evaluations (batched_plain_align).
 
-def nelder_mead(f, x0, scale, max_evals, tol=1e-9):
+def _nelder_mead(x0, scale, max_evals, tol=1e-9):
     """Standard Nelder-Mead (reflection 1, expansion 2, contraction 1/2,
-    shrink 1/2) from the simplex x0 + scale_i e_i.  Returns (x, fx, evals)."""
+    shrink 1/2) from the simplex x0 + scale_i e_i."""
     n = len(x0)
     pts = [np.array(x0, float)] + [np.array(x0, float) + scale[i] * np.eye(n)[i] for i in range(n)]
-    vals = [f(p) for p in pts]
+    vals = []
+    for p in pts:
+        vals.append((yield p))
     evals = n + 1
     while evals < max_evals:
         order = np.argsort(vals)
@@ -105,10 +114,12 @@ def nelder_mead(f, x0, scale, max_evals, tol=1e-9):
             break
         c = np.mean(pts[:-1], axis=0)
         xr = c + (c - pts[-1])
-        fr = f(xr); evals += 1
+        fr = yield xr
+        evals += 1
         if fr < vals[0]:
             xe = c + 2.0 * (c - pts[-1])
-            fe = f(xe); evals += 1
+            fe = yield xe
+            evals += 1
             if fe < fr:
                 pts[-1], vals[-1] = xe, fe
             else:
@@ -117,31 +128,33 @@ def nelder_mead(f, x0, scale, max_evals, tol=1e-9):
             pts[-1], vals[-1] = xr, fr
         else:
             xc = c + 0.5 * (pts[-1] - c) if fr >= vals[-1] else c + 0.5 * (xr - c)
-            fc = f(xc); evals += 1
+            fc = yield xc
+            evals += 1
             if fc < min(fr, vals[-1]):
                 pts[-1], vals[-1] = xc, fc
             else:
                 for i in range(1, len(pts)):
                     pts[i] = pts[0] + 0.5 * (pts[i] - pts[0])
-                    vals[i] = f(pts[i]); evals += 1
+                    vals[i] = yield pts[i]
+                    evals += 1
     i = int(np.argmin(vals))
     return pts[i], vals[i], evals
 
 
-def coordinate_descent(f, x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
+def _coordinate_descent(x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
     """Coordinate descent with per-axis step halving near the minimum."""
     x, fx, evals = np.array(x0, float), f0, 0
     step = np.array(step, float)
     while evals < max_evals and np.any(step > min_step):
-        improved = False
         for i in range(len(x)):
             if step[i] <= min_step:
                 continue
-            for s in (+1.0, -1.0):
-                y = x.copy(); y[i] += s * step[i]
-                fy = f(y); evals += 1
+            for sgn in (+1.0, -1.0):
+                y = x.copy(); y[i] += sgn * step[i]
+                fy = yield y
+                evals += 1
                 if fy < fx:
-                    x, fx, improved = y, fy, True
+                    x, fx = y, fy
                     break
             else:
                 step[i] *= shrink
@@ -150,20 +163,21 @@ def coordinate_descent(f, x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
     return x, fx, evals
 
 
-def hybrid_minimize(f, n=6, budget=700, fd_step=(0.02, 0.02, 0.02, 0.02, 0.02, 0.02),
-                    simplex=(0.05, 0.05, 0.05, 0.05, 0.05, 0.05), gd_iters=2, nm_share=0.6):
+def _hybrid(n=6, budget=700, fd_step=(0.02, 0.02, 0.02, 0.02, 0.02, 0.02),
+            simplex=(0.05, 0.05, 0.05, 0.05, 0.05, 0.05), gd_iters=2, nm_share=0.6):
     """Initial gradient descent by central differences with a backtracking
-    line search, then Nelder-Mead, then coordinate descent (Sec. IV-C).
-    Returns (x, fx, evals)."""
+    line search, then Nelder-Mead, then coordinate descent (Sec. IV-C)."""
     x = np.zeros(n)
-    fx = f(x)
+    fx = yield x
     evals = 1
     h = np.asarray(fd_step, float)
     for _ in range(gd_iters):
         g = np.zeros(n)
         for i in range(n):
             e = np.zeros(n); e[i] = h[i]
-            g[i] = (f(x + e) - f(x - e)) / (2 * h[i])
+            fp = yield x + e
+            fm = yield x - e
+            g[i] = (fp - fm) / (2 * h[i])
             evals += 2
         gn = np.linalg.norm(g / h)
         if gn == 0:
@@ -172,15 +186,40 @@ def hybrid_minimize(f, n=6, budget=700, fd_step=(0.02, 0.02, 0.02, 0.02, 0.02, 0
         t = 1.0
         for _ in range(6):
             y = x + t * d
-            fy = f(y); evals += 1
+            fy = yield y
+            evals += 1
             if fy < fx:
                 x, fx = y, fy
                 break
             t *= 0.5
-    x, fx, e1 = nelder_mead(f, x, np.asarray(simplex, float), int((budget - evals) * nm_share) + evals)
+    x, fx, e1 = yield from _nelder_mead(x, np.asarray(simplex, float), int((budget - evals) * nm_share) + evals)
     evals += e1
-    x2, fx2, e2 = coordinate_descent(f, x, fx, np.asarray(simplex, float) * 0.25, budget - evals)
+    x2, fx2, e2 = yield from _coordinate_descent(x, fx, np.asarray(simplex, float) * 0.25, budget - evals)
     return (x2, fx2, evals + e2) if fx2 <= fx else (x, fx, evals + e2)
+
+
+def _drive(gen, f):
+    try:
+        x = next(gen)
+        while True:
+            x = gen.send(f(x))
+    except StopIteration as stop:
+        return stop.value
+
+
+def nelder_mead(f, x0, scale, max_evals, tol=1e-9):
+    """Nelder-Mead on f; returns (x, fx, evals)."""
+    return _drive(_nelder_mead(x0, scale, max_evals, tol), f)
+
+
+def coordinate_descent(f, x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
+    """Coordinate descent on f from (x0, f0); returns (x, fx, evals)."""
+    return _drive(_coordinate_descent(x0, f0, step, max_evals, shrink, min_step), f)
+
+
+def hybrid_minimize(f, n=6, budget=700, **kw):
+    """The paper's hybrid optimizer on f from x = 0; returns (x, fx, evals)."""
+    return _drive(_hybrid(n, budget, **kw), f)
 
 
 def plain_align(mesh, scan, T0, eps=0.1, budget=700):
@@ -203,6 +242,61 @@ def plain_align(mesh, scan, T0, eps=0.1, budget=700):
     xd.copy_(torch.from_numpy(np.asarray(x, np.float64).reshape(1, 6)))
     R.se3_retract(T0d, xd, out=Td)
     return Td.cpu().numpy().reshape(3, 4), fx, evals
+
+
+def lockstep(gens, evaluate):
+    """Drives optimizer generators together: each round, evaluate(ks, xs)
+    receives the unfinished instances and their next points and returns their
+    costs.  Returns (results per instance, rounds)."""
+    pending = [next(g) for g in gens]
+    result = [None] * len(gens)
+    rounds = 0
+    while True:
+        act = [k for k in range(len(gens)) if result[k] is None]
+        if not act:
+            return result, rounds
+        vals = evaluate(act, [pending[k] for k in act])
+        rounds += 1
+        for k, v in zip(act, vals):
+            try:
+                pending[k] = gens[k].send(float(v))
+            except StopIteration as stop:
+                result[k] = stop.value
+
+
+def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None):
+    """The paper's optimizer for many alignments at once: every instance runs
+    the same hybrid optimizer as plain_align, and each round evaluates the
+    next point of every unfinished instance in one launch (T0: [K,3,4] or
+    [K,12] host poses; scans: one scan, or a list with scan_of[k] the scan of
+    instance k).  Each instance evaluates exactly the points plain_align
+    would.  Returns (T [K,3,4] numpy, E [K], evaluations [K], launches)."""
+    dev = mesh.xyz.device
+    T0 = np.asarray(T0, np.float64).reshape(-1, 12)
+    K = T0.shape[0]
+    if isinstance(scans, R.Scan):
+        scans, scan_of = [scans], [0] * K
+    scan_of = np.asarray(scan_of if scan_of is not None else [0] * K)
+    T0d = torch.from_numpy(T0).to(dev)
+
+    def evaluate(ks, xs):
+        # the active instances grouped by scan, in scan order, as one batched launch
+        order = sorted(range(len(ks)), key=lambda j: scan_of[ks[j]])
+        kk = [ks[j] for j in order]
+        used = sorted(set(scan_of[kk].tolist()))
+        counts = [int((scan_of[kk] == sc).sum()) for sc in used]
+        X = torch.from_numpy(np.stack([xs[j] for j in order])).to(dev)
+        Td = R.se3_retract(T0d[kk].contiguous(), X)
+        out = R.align_cost(mesh, [scans[sc] for sc in used], Td, eps, poses_per_scan=counts)
+        v = out[:, R.OUT_E_TABLE].cpu().numpy()
+        res = np.empty(len(ks))
+        res[order] = v
+        return res
+
+    result, launches = lockstep([_hybrid(budget=budget) for _ in range(K)], evaluate)
+    X = torch.from_numpy(np.stack([r[0] for r in result])).to(dev)
+    T = R.se3_retract(T0d, X).cpu().numpy().reshape(K, 3, 4)
+    return T, np.array([r[1] for r in result]), np.array([r[2] for r in result]), launches
 
 
 def pose_errors(T, T_true):

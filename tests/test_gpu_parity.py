@@ -538,3 +538,22 @@ def test_plain_form_reduces_table_cost(rm):
     dt0, _ = A.pose_errors(T0, w.T_true)
     dt, _ = A.pose_errors(T, w.T_true)
     assert dt[0] < dt0[0]
+
+
+def test_batched_plain_form_matches_plain_form(rm):
+    """The paper's optimizer run for several alignments in lockstep (one
+    batched launch per round) ends at exactly the poses, costs and evaluation
+    counts of running it one alignment at a time."""
+    _say("batched plain form")
+    from paper_1702_06813_amd import align as A
+    w = workload("kinect")
+    dm = _dev_mesh(rm, oracle_map("kinect"))
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(DEV), cam=w.cam)
+    rng = np.random.default_rng(23)
+    starts = np.stack([S.perturb(w.T_true, rng, 0.05, np.deg2rad(2.0), fixed=True) for _ in range(3)])
+    T, E, ev, launches = A.batched_plain_align(dm, scan, starts, eps=EPS, budget=120)
+    for k in range(3):
+        Tk, ek, evk = A.plain_align(dm, scan, starts[k], eps=EPS, budget=120)
+        np.testing.assert_array_equal(Tk, T[k])
+        assert ek == E[k] and evk == ev[k]
+    assert launches == ev.max()

@@ -46,3 +46,19 @@ def test_pose_errors():
     T2 = T.copy(); T2[:, :3] = Rotation.from_rotvec([0, 0, 0.1]).as_matrix(); T2[:, 3] = [0.03, 0.04, 0]
     dt, ang = A.pose_errors(T2, T)
     assert abs(dt[0] - 0.05) < 1e-12 and abs(ang[0] - 0.1) < 1e-9
+
+
+def test_lockstep_equals_one_at_a_time():
+    """Driving several hybrid optimizers together (one batched evaluation per
+    round) gives each exactly the result it reaches alone, in as many rounds
+    as the longest instance needs."""
+    rng = np.random.default_rng(4)
+    cs = [rng.normal(scale=0.03, size=6) for _ in range(5)]
+    fs = [lambda x, c=c: float(np.floor(2e4 * np.sum((x - c) ** 2))) for c in cs]
+    alone = [A.hybrid_minimize(f, budget=300) for f in fs]
+    res, rounds = A.lockstep([A._hybrid(budget=300) for _ in fs],
+                             lambda ks, xs: [fs[k](x) for k, x in zip(ks, xs)])
+    for (x1, f1, e1), (x2, f2, e2) in zip(alone, res):
+        np.testing.assert_array_equal(x1, x2)
+        assert f1 == f2 and e1 == e2
+    assert rounds == max(e for _, _, e in alone)
