@@ -275,7 +275,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
         if (persistent) {
             int32_t* order = at<int32_t>(ctx, o_ord);
-            RM_HIP(ctx, launch_order(ctx->stream, bin_small, bin_big, R, hist, order));
+            RM_HIP(ctx, launch_order(ctx->stream, bd, bin_small, bin_big, R, hist, order));
             a.order = order;
         }
         if (!check || attempt > 0) break;

@@ -97,8 +97,8 @@ hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a);
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode);
 // Longest-first order of the records of a binned call: counting sort of the
 // records by log2 of their bin fill, descending.  hist: 32 zeroed counters.
-hipError_t launch_order(hipStream_t st, const int32_t* bin_small, const int32_t* bin_big, int64_t n_records,
-                        int32_t* hist, int32_t* order);
+hipError_t launch_order(hipStream_t st, const BatchDesc& bd, const int32_t* bin_small, const int32_t* bin_big,
+                        int64_t n_records, int32_t* hist, int32_t* order);
 // Workgroups of the persistent rasterizer that fit on the device at once.
 int persistent_grid(int tile_w, int tile_h, int mode);
 hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec,

@@ -1184,13 +1184,24 @@ __global__ void k_order_offsets(int32_t* hist) {
     }
 }
 
-__global__ void __launch_bounds__(kWG) k_order_scatter(const int32_t* __restrict__ bs, const int32_t* __restrict__ bb,
-                                                       int64_t n, int32_t* __restrict__ hist,
-                                                       int32_t* __restrict__ order) {
+// Records are visited in item order (per scan tile-major, poses of a tile
+// adjacent), so that each workgroup's run of a bucket keeps neighbouring poses
+// of the same tiles, which read the same triangles, together.
+__global__ void __launch_bounds__(kWG) k_order_scatter(BatchDesc bd, const int32_t* __restrict__ bs,
+                                                       const int32_t* __restrict__ bb, int64_t n,
+                                                       int32_t* __restrict__ hist, int32_t* __restrict__ order) {
     __shared__ int h[kOrderBuckets], base[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t item = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    int64_t r = n;
+    if (item < n) {
+        int sc = 0;
+        while (sc + 1 < bd.n_scans && item >= bd.s[sc + 1].item_off) ++sc;
+        const ScanDesc& sd = bd.s[sc];
+        const int64_t local = item - sd.item_off;
+        r = sd.rec_off + (local % sd.n_poses) * (int64_t)(sd.tiles_x * sd.tiles_y) + local / sd.n_poses;
+    }
     const int b = r < n ? order_bucket(bs, bb, r) : 0;
     if (r < n) atomicAdd(&h[b], 1);
     __syncthreads();
@@ -1231,13 +1242,13 @@ hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) 
     return launch_bin_t<32, 32>(st, bd, a);
 }
 
-hipError_t launch_order(hipStream_t st, const int32_t* bin_small, const int32_t* bin_big, int64_t n_records,
-                        int32_t* hist, int32_t* order) {
+hipError_t launch_order(hipStream_t st, const BatchDesc& bd, const int32_t* bin_small, const int32_t* bin_big,
+                        int64_t n_records, int32_t* hist, int32_t* order) {
     if (n_records <= 0) return hipSuccess;
     const unsigned g = (unsigned)((n_records + kWG - 1) / kWG);
     hipLaunchKernelGGL(k_order_count, dim3(g), dim3(kWG), 0, st, bin_small, bin_big, n_records, hist);
     hipLaunchKernelGGL(k_order_offsets, dim3(1), dim3(64), 0, st, hist);
-    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(kWG), 0, st, bin_small, bin_big, n_records, hist, order);
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(kWG), 0, st, bd, bin_small, bin_big, n_records, hist, order);
     return hipGetLastError();
 }
 
