@@ -561,7 +561,7 @@ __device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
 // rectangle, then reserved with one global atomic per (workgroup, tile,
 // class).  Small footprints fill a bin from the front, large ones from the
 // back, so that the tile pass sees triangles of similar cost together.
-constexpr float kBigFootprint = 144.0f;    // margin-widened bounding box area, px
+constexpr float kBigFootprint = 100.0f;    // margin-widened bounding box area, px
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
