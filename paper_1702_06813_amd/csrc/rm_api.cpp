@@ -190,7 +190,8 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
     ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
 }
 
-// One scoring pass: cull, bin, rasterize (+ fused comparison), reduce.
+// One scoring pass: cull, near-to-far cluster order, bin, rasterize (+ fused
+// comparison), reduce.
 int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
              float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
     plan(bd, tw, th);
@@ -223,6 +224,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         const size_t o_cnt = cv.take<int32_t>(n_cnt);
         const size_t o_ord = cv.take<int32_t>(persistent ? R : 1);
         const size_t o_vis = cv.take<uint2>((int64_t)P * C);
+        const size_t o_visz = cv.take<float>((int64_t)P * C);
         const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
         const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
         const size_t o_bin = cv.take<uint32_t>(R * cap);
@@ -247,7 +249,9 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
                                 : nullptr;
         RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, n_cnt));
         uint2* vis = at<uint2>(ctx, o_vis);
-        RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_count, vis_tris));
+        float* vis_z = at<float>(ctx, o_visz);
+        RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_z, vis_count, vis_tris));
+        RM_HIP(ctx, launch_vis_sort(ctx->stream, bd, (int32_t)C, vis_count, vis_z, vis));
         a.xyz = mesh->xyz;
         a.tri = mesh->tri;
         a.cls = mesh->cls;

@@ -90,9 +90,10 @@ int64_t prepared_normals_offset(int64_t n_tris);
 hipError_t launch_prepare(hipStream_t st, const float* xyz, int64_t n_vertices, const int32_t* tri,
                           int64_t n_tris, void* out);
 hipError_t launch_zero_i32(hipStream_t st, int32_t* p, int64_t n);
-hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds* cb,
-                       int32_t n_clusters, const double* T_wc, uint2* vis, int32_t* vis_count,
-                       int32_t* vis_tris);
+hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds* cb, int32_t n_clusters,
+                       const double* T_wc, uint2* vis, float* vis_z, int32_t* vis_count, int32_t* vis_tris);
+hipError_t launch_vis_sort(hipStream_t st, const BatchDesc& bd, int32_t n_clusters, const int32_t* vis_count,
+                           const float* vis_z, uint2* vis);
 hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a);
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode);
 // Longest-first order of the records of a binned call: counting sort of the

@@ -787,9 +787,11 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     const int ns = a.bin_small[it.rec], nb = a.bin_big[it.rec];
     if (tid == 0) atomicMax(a.bin_max, ns + nb);
 
-    // Rounds of kWG triangles: from the (pose, tile) bin (small footprints at
-    // the front, large at the back), or, if the bin overflowed its capacity,
-    // every triangle of every visible cluster of the pose (slower, same result).
+    // Rounds of kWG triangles: from the (pose, tile) bin, large footprints
+    // (held at its back) before small ones (at its front), so that near
+    // surfaces reach the depth snapshot early; or, if the bin overflowed its
+    // capacity, every triangle of every visible cluster of the pose (slower,
+    // same result).
     const bool use_bin = ns + nb <= a.bin_cap;
     const int nvis = a.vis_count[it.pose];
     const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
@@ -800,7 +802,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         if (use_bin) {
             const int i = r * kWG + tid;
             if (i >= ns + nb) return -1;
-            return (int32_t)(i < ns ? bin[i] : bin[a.bin_cap - 1 - (i - ns)]);
+            return (int32_t)(i < nb ? bin[a.bin_cap - 1 - i] : bin[i - nb]);
         }
         const int64_t t = (int64_t)vis[r].x * kClusterTris + tid;
         return t < a.n_tris ? (int32_t)t : -1;
@@ -1017,8 +1019,8 @@ __device__ __forceinline__ void proj_acc(double fx, double fy, double cx, double
 // screen rectangle is widened by 2 px.
 __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds* __restrict__ cb,
                                               int32_t n_clusters, const double* __restrict__ T_wc,
-                                              uint2* __restrict__ vis, int32_t* __restrict__ vis_count,
-                                              int32_t* __restrict__ vis_tris) {
+                                              uint2* __restrict__ vis, float* __restrict__ vis_z,
+                                              int32_t* __restrict__ vis_count, int32_t* __restrict__ vis_tris) {
     const int c = blockIdx.x * kWG + threadIdx.x;
     const int pose = blockIdx.y;
     int s = 0;
@@ -1027,6 +1029,7 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
     bool visible = false;
     uint32_t rect = 0;
     int ntri = 0;
+    float znear = 0.0f;                        // nearest box corner depth (ordering key only)
     if (c < n_clusters) {
         const ClusterBounds b = cb[c];
         ntri = b.n_tris;
@@ -1046,6 +1049,7 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
             nfront += Z[k] >= zn;
             nfar += Z[k] > zf;
         }
+        znear = (float)fmax(fmin(fmin(fmin(Z[0], Z[1]), fmin(Z[2], Z[3])), fmin(fmin(Z[4], Z[5]), fmin(Z[6], Z[7]))), zn);
         const double fx = sd.fx, fy = sd.fy, cx = sd.cx, cy = sd.cy;
         double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
         if (nfront > 0 && nfar < 8 && b.n_tris > 0) {
@@ -1091,7 +1095,77 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
         atomicAdd(vis_tris + pose, ntv);
     }
     base = __shfl(base, 0);
-    if (visible) vis[(int64_t)pose * n_clusters + base + __popcll(m & ((1ull << lane) - 1ull))] = make_uint2((uint32_t)c, rect);
+    if (visible) {
+        const int64_t slot = (int64_t)pose * n_clusters + base + __popcll(m & ((1ull << lane) - 1ull));
+        vis[slot] = make_uint2((uint32_t)c, rect);
+        vis_z[slot] = znear;
+    }
+}
+
+// Near-to-far order of each pose's visible clusters: a counting sort on the
+// logarithm of the nearest box corner depth.  The tile bins are filled in
+// this order, so the rasterizer meets near surfaces first and its depth
+// snapshot rejects more of what lies behind them.  Only speed depends on the
+// order; a pose with more visible clusters than one workgroup stages keeps
+// the order of the cull.
+constexpr int kVisSortWG = 1024;
+constexpr int kVisSortMax = 7680;              // 60 KB of LDS staging
+constexpr int kVisBuckets = 256;
+
+__global__ void __launch_bounds__(kVisSortWG) k_vis_sort(BatchDesc bd, int32_t n_clusters,
+                                                         const int32_t* __restrict__ vis_count,
+                                                         const float* __restrict__ vis_z, uint2* __restrict__ vis) {
+    __shared__ uint2 stage[kVisSortMax];
+    __shared__ int cur[kVisBuckets];
+    const int pose = blockIdx.x;
+    const int n = vis_count[pose];
+    if (n <= 1 || n > kVisSortMax) return;
+    const ScanDesc& sd = bd.s[pose_scan(bd, pose)];
+    const float lz0 = log2f(sd.z_near);
+    const float scale = (float)kVisBuckets / fmaxf(log2f(sd.z_far) - lz0, 1e-3f);
+    for (int i = threadIdx.x; i < kVisBuckets; i += kVisSortWG) cur[i] = 0;
+    __syncthreads();
+    uint2* v = vis + (int64_t)pose * n_clusters;
+    const float* z = vis_z + (int64_t)pose * n_clusters;
+    constexpr int kPer = (kVisSortMax + kVisSortWG - 1) / kVisSortWG;
+    uint2 e[kPer];
+    int b[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * kVisSortWG;
+        b[k] = 0;
+        if (i < n) {
+            e[k] = v[i];
+            const float f = (log2f(z[i]) - lz0) * scale;
+            b[k] = f >= (float)(kVisBuckets - 1) ? kVisBuckets - 1 : (f > 0.0f ? (int)f : 0);
+            atomicAdd(&cur[b[k]], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {                    // exclusive prefix over the buckets, 4 per lane
+        const int l = threadIdx.x;
+        const int c0 = cur[4 * l], c1 = cur[4 * l + 1], c2 = cur[4 * l + 2], c3 = cur[4 * l + 3];
+        const int tot = c0 + c1 + c2 + c3;
+        int inc = tot;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(inc, off);
+            if (l >= off) inc += y;
+        }
+        const int ex = inc - tot;
+        cur[4 * l] = ex;
+        cur[4 * l + 1] = ex + c0;
+        cur[4 * l + 2] = ex + c0 + c1;
+        cur[4 * l + 3] = ex + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * kVisSortWG;
+        if (i < n) stage[atomicAdd(&cur[b[k]], 1)] = e[k];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kVisSortWG) v[i] = stage[i];
 }
 
 // ------------------------------------------------------------------ per-pose reduction
@@ -1228,10 +1302,18 @@ hipError_t launch_raster_t(hipStream_t st, const BatchDesc& bd, const RasterArgs
 }  // namespace
 
 hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds* cb, int32_t n_clusters,
-                       const double* T_wc, uint2* vis, int32_t* vis_count, int32_t* vis_tris) {
+                       const double* T_wc, uint2* vis, float* vis_z, int32_t* vis_count, int32_t* vis_tris) {
     if (n_clusters == 0) return hipSuccess;
     const dim3 grid((unsigned)((n_clusters + kWG - 1) / kWG), (unsigned)bd.n_poses);
-    hipLaunchKernelGGL(k_cull, grid, dim3(kWG), 0, st, bd, cb, n_clusters, T_wc, vis, vis_count, vis_tris);
+    hipLaunchKernelGGL(k_cull, grid, dim3(kWG), 0, st, bd, cb, n_clusters, T_wc, vis, vis_z, vis_count, vis_tris);
+    return hipGetLastError();
+}
+
+hipError_t launch_vis_sort(hipStream_t st, const BatchDesc& bd, int32_t n_clusters, const int32_t* vis_count,
+                           const float* vis_z, uint2* vis) {
+    if (n_clusters <= 1 || bd.n_poses == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vis_sort, dim3((unsigned)bd.n_poses), dim3(kVisSortWG), 0, st, bd, n_clusters, vis_count,
+                       vis_z, vis);
     return hipGetLastError();
 }
 
