@@ -269,29 +269,45 @@ __device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const 
     }
 }
 
+// Triangles that cover much of the tile.  Thread t keeps pixel column
+// t % TW and steps through rows t / TW, t / TW + kWG / TW, ... of every such
+// triangle, so that the plane and edge functions advance by additions and a
+// pixel already holding a nearer key is rejected before its edge test (the
+// triangles come roughly near to far).
 template <int TW, int TH>
-__device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Tile& tl, const float* rmin,
-                                           double cx, double cy, float w_far) {
+__device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Tile& tl, double cx, double cy,
+                                           float w_far) {
+    static_assert(kWG % TW == 0, "a thread keeps one column");
+    constexpr int S = kWG / TW;
+    const int x = threadIdx.x % TW, yt = threadIdx.x / TW;
     const int nq = min(q.n, kFatCap);
     for (int b = 0; b < nq; ++b) {
         const uint32_t box = q.box[b];
         const int bx0 = (int)(box & 0xff), bx1 = (int)((box >> 8) & 0xff);
         const int by0 = (int)((box >> 16) & 0xff), by1 = (int)(box >> 24);
-        for (int p = threadIdx.x + by0 * TW; p < (by1 + 1) * TW; p += kWG) {
-            const int y = p / TW, x = p % TW;              // TW is a power of two
-            if (x < bx0 || x > bx1) continue;
-            // farther than the row's farthest key at the round start: the
-            // atomic could not change the pixel, covered or not
-            const float wf = (float)fma(q.pb[b], (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
-            if (wf < rmin[y * kSegs + x / kSeg] || wf < w_far) continue;
-            const int ry = y - by0, rx = x - bx0;
-            bool in = true;
+        if (x < bx0 || x > bx1) continue;
+        int y = yt + ((by0 - yt + S - 1) / S) * S;          // first row >= by0 of this thread
+        if (y > by1) continue;
+        const int ry = y - by0, rx = x - bx0;
+        int64_t e[3], se[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int64_t e = q.E[k][b] + 256 * ((int64_t)q.dx[k][b] * ry - (int64_t)q.dy[k][b] * rx);
-                in &= e >= 0;
-            }
-            if (in) atomicMin((unsigned long long*)(keys + y * TW + x), (unsigned long long)pack_key(wf, q.id[b]));
+        for (int k = 0; k < 3; ++k) {
+            e[k] = q.E[k][b] + 256 * ((int64_t)q.dx[k][b] * ry - (int64_t)q.dy[k][b] * rx);
+            se[k] = 256 * S * (int64_t)q.dx[k][b];
+        }
+        const double pb = q.pb[b];
+        double w = fma(pb, (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
+        const double dw = pb * (double)S;
+        const uint32_t id = q.id[b];
+        uint64_t* k = keys + y * TW + x;
+        for (; y <= by1; y += S) {
+            const float wf = (float)w;
+            const uint64_t nk = pack_key(wf, id);
+            if (((e[0] | e[1] | e[2]) >= 0) & (wf >= w_far) & (nk < *k))
+                atomicMin((unsigned long long*)k, (unsigned long long)nk);
+            e[0] += se[0]; e[1] += se[1]; e[2] += se[2];
+            w += dw;
+            k += S * TW;
         }
     }
 }
@@ -829,7 +845,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         if (cur.t >= 0) raster_triangle(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
         __syncthreads();
         if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
-        if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, rmin, dcx, dcy, w_far);
+        if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, dcx, dcy, w_far);
         __syncthreads();
         // row and tile snapshot for the next round (w >= 0, so its bits order
         // like its value)
