@@ -632,32 +632,40 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
                 }
             }
         }
-        // tiles the footprint touches, as a bit mask over its tile rectangle when it fits in 64 bits
-        const int sw = tx1 - tx0 + 1, nspan = ok ? sw * (ty1 - ty0 + 1) : 0;
+        // tiles the footprint touches: a bit mask over its tile rectangle with
+        // rows at a power-of-two stride (bit r << ls | c for tile (tx0 + c,
+        // ty0 + r)) when that fits in 64 bits, otherwise tested again per pass
+        const int sw = tx1 - tx0 + 1, sh = ty1 - ty0 + 1;
+        const int nspan = ok ? sw * sh : 0;
+        const int ls = sw <= 1 ? 0 : 32 - __clz(sw - 1);
+        const bool masked = (sh << ls) <= 64;
         const bool test_tiles = nspan > 2 && fabsf(area2) > 1e-3f;
+        auto hit = [&](int tx, int ty) {
+            return !test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
+                                            (float)(ty * TH + TH - 1));
+        };
         uint64_t hits = 0;
-        if (nspan <= 64) {
-            for (int i = 0; i < nspan; ++i) {
-                const int tx = tx0 + i % sw, ty = ty0 + i / sw;
-                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
-                                             (float)(ty * TH + TH - 1)))
-                    hits |= 1ull << i;
+        if (nspan > 0 && masked) {
+            if (!test_tiles) {
+                const uint64_t row = ~0ull >> (64 - sw);
+                for (int r = 0; r < sh; ++r) hits |= row << (r << ls);
+            } else {
+                for (int r = 0; r < sh; ++r)
+                    for (int c = 0; c < sw; ++c)
+                        if (hit(tx0 + c, ty0 + r)) hits |= 1ull << ((r << ls) | c);
             }
         }
         const uint32_t inc = big ? 0x10000u : 1u;
         __syncthreads();
-        if (nspan <= 64) {
+        if (masked) {
             for (uint64_t m = hits; m; m &= m - 1) {      // only the tiles hit
                 const int i = __ffsll((unsigned long long)m) - 1;
-                atomicAdd(&tcnt[(ty0 + i / sw - ry0) * rw + (tx0 + i % sw - rx0)], inc);
+                atomicAdd(&tcnt[(ty0 + (i >> ls) - ry0) * rw + (tx0 + (i & ((1 << ls) - 1)) - rx0)], inc);
             }
         } else {
-            for (int i = 0; i < nspan; ++i) {
-                const int tx = tx0 + i % sw, ty = ty0 + i / sw;
-                if (!test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
-                                             (float)(ty * TH + TH - 1)))
-                    atomicAdd(&tcnt[(ty - ry0) * rw + (tx - rx0)], inc);
-            }
+            for (int r = 0; r < sh; ++r)
+                for (int c = 0; c < sw; ++c)
+                    if (hit(tx0 + c, ty0 + r)) atomicAdd(&tcnt[(ty0 + r - ry0) * rw + (tx0 + c - rx0)], inc);
         }
         __syncthreads();
         int fs = 0, fb = 0;                    // largest fills this thread reserved
@@ -688,17 +696,7 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
             }
         }
         __syncthreads();
-        uint64_t m = hits;
-        for (int i = 0; nspan <= 64 ? m != 0 : i < nspan; ++i) {
-            if (nspan <= 64) {                              // only the tiles hit
-                i = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1;
-            }
-            const int tx = tx0 + i % sw, ty = ty0 + i / sw;
-            if (nspan > 64 && test_tiles &&
-                !foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
-                           (float)(ty * TH + TH - 1)))
-                continue;
+        auto put = [&](int tx, int ty) {
             const int li = (ty - ry0) * rw + (tx - rx0);
             const uint32_t old = atomicAdd(&tcnt[li], inc);
             uint32_t* bin = a.bins + (rec0 + ty * sd.tiles_x + tx) * (int64_t)cap;
@@ -709,6 +707,16 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
                 const uint32_t slot = tbs[li] + (old & 0xffffu);
                 if (slot < cap) bin[slot] = (uint32_t)t;
             }
+        };
+        if (masked) {
+            for (uint64_t m = hits; m; m &= m - 1) {
+                const int i = __ffsll((unsigned long long)m) - 1;
+                put(tx0 + (i & ((1 << ls) - 1)), ty0 + (i >> ls));
+            }
+        } else {
+            for (int r = 0; r < sh; ++r)
+                for (int c = 0; c < sw; ++c)
+                    if (hit(tx0 + c, ty0 + r)) put(tx0 + c, ty0 + r);
         }
     }
 }
