@@ -547,21 +547,43 @@ __device__ __forceinline__ bool footprint(const PoseF& P, const CamF& cam, float
     return true;
 }
 
-// True unless the footprint polygon certainly misses the rectangle of pixel
-// centres [x0, x1] x [y0, y1] (widened by 2 px).
-__device__ __forceinline__ bool foot_hits(const Foot& f, float area2, float x0, float x1, float y0, float y1) {
-    x0 -= 2.0f; y0 -= 2.0f; x1 += 2.0f; y1 += 2.0f;
+// Edge functions of the footprint polygon for the tile test: tile (tx, ty),
+// its pixel centres widened by 2 px, certainly misses the polygon when for
+// some edge A x + B y + K < 0 at x = tx * TW, y = ty * TH (A, B the inward
+// normal, K the offset to the rectangle corner farthest inside plus a
+// tolerance above the float rounding of the evaluation).  Degenerate edges
+// of a repeated vertex never exclude a tile.
+struct FootEdges {
+    float A[4], B[4], K[4];
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ FootEdges foot_edges(const Foot& f, float area2, float W, float H) {
     const float sg = area2 > 0.0f ? 1.0f : -1.0f;
-    bool hit = true;
+    FootEdges g;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int j = (i + 1) & 3;
         const float A = -sg * (f.v[j] - f.v[i]), B = sg * (f.u[j] - f.u[i]);
-        const float xs = A > 0.0f ? x1 : x0, ys = B > 0.0f ? y1 : y0;
-        const float e = A * (xs - f.u[i]) + B * (ys - f.v[i]);
-        const float tol = 1e-4f * (fabsf(A) * fabsf(xs - f.u[i]) + fabsf(B) * fabsf(ys - f.v[i])) + 1e-6f;
-        hit &= !(e < -tol);
+        const float ox = A > 0.0f ? (float)(TW + 1) : -2.0f, oy = B > 0.0f ? (float)(TH + 1) : -2.0f;
+        const float tol = 1e-4f * (fabsf(A) + fabsf(B)) * (fabsf(f.u[i]) + fabsf(f.v[i]) + W + H + 8.0f) + 1e-6f;
+        g.A[i] = A;
+        g.B[i] = B;
+        g.K[i] = A * (ox - f.u[i]) + B * (oy - f.v[i]) + tol;
     }
+    return g;
+}
+
+// Row part of the test: K + B y for the tile row at y = ty * TH.
+__device__ __forceinline__ void edges_row(const FootEdges& g, float y, float k[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) k[i] = fmaf(g.B[i], y, g.K[i]);
+}
+
+__device__ __forceinline__ bool edges_hit(const FootEdges& g, const float k[4], float x) {
+    bool hit = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) hit &= !(fmaf(g.A[i], x, k[i]) < 0.0f);
     return hit;
 }
 
@@ -640,19 +662,19 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
         const int ls = sw <= 1 ? 0 : 32 - __clz(sw - 1);
         const bool masked = (sh << ls) <= 64;
         const bool test_tiles = nspan > 2 && fabsf(area2) > 1e-3f;
-        auto hit = [&](int tx, int ty) {
-            return !test_tiles || foot_hits(f, area2, (float)(tx * TW), (float)(tx * TW + TW - 1), (float)(ty * TH),
-                                            (float)(ty * TH + TH - 1));
-        };
+        const FootEdges g = foot_edges<TW, TH>(f, area2, (float)cam.W, (float)cam.H);
         uint64_t hits = 0;
         if (nspan > 0 && masked) {
             if (!test_tiles) {
                 const uint64_t row = ~0ull >> (64 - sw);
                 for (int r = 0; r < sh; ++r) hits |= row << (r << ls);
             } else {
-                for (int r = 0; r < sh; ++r)
+                for (int r = 0; r < sh; ++r) {
+                    float k[4];
+                    edges_row(g, (float)((ty0 + r) * TH), k);
                     for (int c = 0; c < sw; ++c)
-                        if (hit(tx0 + c, ty0 + r)) hits |= 1ull << ((r << ls) | c);
+                        if (edges_hit(g, k, (float)((tx0 + c) * TW))) hits |= 1ull << ((r << ls) | c);
+                }
             }
         }
         const uint32_t inc = big ? 0x10000u : 1u;
@@ -663,9 +685,13 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
                 atomicAdd(&tcnt[(ty0 + (i >> ls) - ry0) * rw + (tx0 + (i & ((1 << ls) - 1)) - rx0)], inc);
             }
         } else {
-            for (int r = 0; r < sh; ++r)
+            for (int r = 0; r < sh; ++r) {
+                float k[4];
+                edges_row(g, (float)((ty0 + r) * TH), k);
                 for (int c = 0; c < sw; ++c)
-                    if (hit(tx0 + c, ty0 + r)) atomicAdd(&tcnt[(ty0 + r - ry0) * rw + (tx0 + c - rx0)], inc);
+                    if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW)))
+                        atomicAdd(&tcnt[(ty0 + r - ry0) * rw + (tx0 + c - rx0)], inc);
+            }
         }
         __syncthreads();
         int fs = 0, fb = 0;                    // largest fills this thread reserved
@@ -714,9 +740,12 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
                 put(tx0 + (i & ((1 << ls) - 1)), ty0 + (i >> ls));
             }
         } else {
-            for (int r = 0; r < sh; ++r)
+            for (int r = 0; r < sh; ++r) {
+                float k[4];
+                edges_row(g, (float)((ty0 + r) * TH), k);
                 for (int c = 0; c < sw; ++c)
-                    if (hit(tx0 + c, ty0 + r)) put(tx0 + c, ty0 + r);
+                    if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW))) put(tx0 + c, ty0 + r);
+            }
         }
     }
 }
