@@ -169,8 +169,6 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
 constexpr int kQCap = kWG + 32;            // queued sub-triangles per round (more go in-thread)
 constexpr int kBand = 2;                   // rows per job
 constexpr int kSmallArea = 64;             // bounding-box pixels rasterized by the owning thread
-constexpr int kFatPixels = 256;            // estimated covered pixels that send a triangle to the fat path
-constexpr int kFatCap = 32;
 
 constexpr int kMaxBands = 16;             // tile height / kBand for the tallest tile (32 rows)
 static_assert(32 / kBand <= kMaxBands && kMaxBands <= 16, "job records hold a 4-bit band index");
@@ -184,16 +182,6 @@ struct BigQueue {
     uint32_t box[kQCap];                   // tile-relative px0 | px1 << 8 | py0 << 16 | py1 << 24
     uint16_t job[kQCap * kMaxBands];       // queued entry << 4 | band, only bands the entry covers
     int n, njobs;
-};
-
-// Triangles that cover much of the tile: one pixel centre per thread at a time.
-struct FatQueue {
-    int64_t E[3][kFatCap];                 // edge functions at (px0, py0)
-    int dx[3][kFatCap], dy[3][kFatCap];
-    double pa[kFatCap], pb[kFatCap], pe[kFatCap];
-    uint32_t id[kFatCap];
-    uint32_t box[kFatCap];
-    int n;
 };
 
 // Rows r0..r1 (tile-relative) of one sub-triangle with tile-relative snapped
@@ -269,54 +257,10 @@ __device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const 
     }
 }
 
-// Triangles that cover much of the tile.  Thread t keeps pixel column
-// t % TW and steps through rows t / TW, t / TW + kWG / TW, ... of every such
-// triangle, so that the plane and edge functions advance by additions and a
-// pixel already holding a nearer key is rejected before its edge test (the
-// triangles come roughly near to far).
-template <int TW, int TH>
-__device__ __forceinline__ void raster_fat(uint64_t* keys, FatQueue& q, const Tile& tl, double cx, double cy,
-                                           float w_far) {
-    static_assert(kWG % TW == 0, "a thread keeps one column");
-    constexpr int S = kWG / TW;
-    const int x = threadIdx.x % TW, yt = threadIdx.x / TW;
-    const int nq = min(q.n, kFatCap);
-    for (int b = 0; b < nq; ++b) {
-        const uint32_t box = q.box[b];
-        const int bx0 = (int)(box & 0xff), bx1 = (int)((box >> 8) & 0xff);
-        const int by0 = (int)((box >> 16) & 0xff), by1 = (int)(box >> 24);
-        if (x < bx0 || x > bx1) continue;
-        int y = yt + ((by0 - yt + S - 1) / S) * S;          // first row >= by0 of this thread
-        if (y > by1) continue;
-        const int ry = y - by0, rx = x - bx0;
-        int64_t e[3], se[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            e[k] = q.E[k][b] + 256 * ((int64_t)q.dx[k][b] * ry - (int64_t)q.dy[k][b] * rx);
-            se[k] = 256 * S * (int64_t)q.dx[k][b];
-        }
-        const double pb = q.pb[b];
-        double w = fma(pb, (double)(tl.y0 + y) - cy, fma(q.pa[b], (double)(tl.x0 + x) - cx, q.pe[b]));
-        const double dw = pb * (double)S;
-        const uint32_t id = q.id[b];
-        uint64_t* k = keys + y * TW + x;
-        for (; y <= by1; y += S) {
-            const float wf = (float)w;
-            const uint64_t nk = pack_key(wf, id);
-            if (((e[0] | e[1] | e[2]) >= 0) & (wf >= w_far) & (nk < *k))
-                atomicMin((unsigned long long*)k, (unsigned long long)nk);
-            e[0] += se[0]; e[1] += se[1]; e[2] += se[2];
-            w += dw;
-            k += S * TW;
-        }
-    }
-}
-
 // Setup of one (sub-)triangle of the contract: snap, orientation, bounding
 // box inside the tile, then the rasterization path by size.
 struct Queues {
     BigQueue big;
-    FatQueue fat;
     // per kSeg-pixel segment of each tile row, the farthest w = 1/z held by
     // its keys (0 if a pixel is empty) at the start of the round, and at
     // kSnapTile the tile's farthest; two buffers, one filled per round
@@ -346,34 +290,6 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     if (boxpx <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
         raster_small(keys, tile_w, tl, rmin, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far, id);
         return;
-    }
-    // fat: many covered pixels in the tile and thick (2 area / longest edge > 8 px)
-    double l2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int i1 = i == 2 ? 0 : i + 1;
-        const double ex = (double)(X[i1] - X[i]), ey = (double)(Y[i1] - Y[i]);
-        l2 = fmax(l2, ex * ex + ey * ey);
-    }
-    const double area_px = (double)area * (0.5 / 65536.0);
-    if (boxpx > kFatPixels && area_px > kFatPixels && (double)area * (double)area > 64.0 * 65536.0 * l2) {
-        const int k = atomicAdd(&Q.fat.n, 1);
-        if (k < kFatCap) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int i1 = i == 2 ? 0 : i + 1;
-                const int dx = X[i1] - X[i], dy = Y[i1] - Y[i];
-                const bool topleft = dy < 0 || (dy == 0 && dx > 0);
-                Q.fat.E[i][k] = (int64_t)dx * (int64_t)(256 * py0 - Y[i]) - (int64_t)dy * (int64_t)(256 * px0 - X[i]) -
-                                (topleft ? 0 : 1);
-                Q.fat.dx[i][k] = dx;
-                Q.fat.dy[i][k] = dy;
-            }
-            Q.fat.pa[k] = pl.a; Q.fat.pb[k] = pl.b; Q.fat.pe[k] = pl.e;
-            Q.fat.id[k] = id;
-            Q.fat.box[k] = box;
-            return;
-        }
     }
     int Xr[3], Yr[3];
     double m[3];
@@ -872,7 +788,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     t2 = entry(2);
     if (tid <= kSnapTile) q.rowmin[0][tid] = 0.0f;   // round 0 sees an empty buffer
     for (int r = 0; r < nr; ++r) {
-        if (tid == 0) { q.big.n = 0; q.big.njobs = 0; q.fat.n = 0; }
+        if (tid == 0) { q.big.n = 0; q.big.njobs = 0; }
         if (tid <= kSnapTile) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
         const float* rmin = q.rowmin[r & 1];
         load_vertices(a.xyz, a.nrm, t1, I1, nxt);
@@ -882,7 +798,6 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         if (cur.t >= 0) raster_triangle(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
         __syncthreads();
         if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
-        if (q.fat.n) raster_fat<TW, TH>(keys, q.fat, tl, dcx, dcy, w_far);
         __syncthreads();
         // row and tile snapshot for the next round (w >= 0, so its bits order
         // like its value)
