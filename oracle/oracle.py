@@ -11,7 +11,12 @@ Pieces, each following the paper:
     and the total error E(X) = sum over pixels (Sec. IV-B);
   * E_soft, a continuous surrogate of E(X) (the paper invites reshaping the
     per-pixel cost, Sec. IV-C) with its se(3) gradient and the Gauss-Newton
-    blocks J^T J / J^T r; and SE(3) exp for pose increments.
+    blocks J^T J / J^T r; and SE(3) exp for pose increments;
+  * the render-accelerated point-to-plane ICP of Sec. V: downsampling,
+    Gaussian smoothing and the depth-image normals of Eq. (2), per-vertex
+    normals, projective association with a depth tolerance, the cost
+    C = sum |Z_M - Z_1| and the point-to-plane Gauss-Newton blocks (readings
+    in the section below).
 
 E_soft (a project definition; the paper optimizes E derivative-free):
     rho_p = 2 * min(r_p^2 / eps^2, 1) - 1   on the three scored cells,
@@ -381,3 +386,173 @@ def fd_jacobian(mesh, cam, T_wc, pixels, scan_d, scan_c, h=1e-4, mode="contract"
         fd[:, k] = (ep - em) / (2 * h)
         stable &= (rp["id"] == base["id"]) & (rm["id"] == base["id"])
     return fd, stable, t0
+
+# --------------------------------------------------------------------------
+# Sec. V: render-accelerated point-to-plane ICP
+# --------------------------------------------------------------------------
+#
+# Sequential depth-image alignment (Sec. V-B): downsample a depth image by 2
+# and drop far points; estimate its normals by Eq. (2); render its mesh, each
+# pixel carrying the normal of the surface it sees; associate every return of
+# the next depth image with the rendered surface at the same pixel when their
+# depths differ by less than a tolerance (projective correspondence, Sec. V);
+# minimize the point-to-plane error of the associated pairs over the pose.
+#
+# Readings (the text is silent or garbled on these):
+#   * downsampling keeps every second pixel of every second row; a pixel
+#     that is not a finite positive depth up to z_max becomes NaN;
+#   * Gaussian smoothing renormalizes the weights over the valid pixels of
+#     the (2R+1)^2 window; an invalid centre stays NaN;
+#   * Eq. (2) takes the tangents (dx, 0, dz_x) and (0, dy, dz_y) with the
+#     central differences dz_x = z~(u+1, v) - z~(u-1, v), dz_y alike, and the
+#     metric steps dx = 2 z~/fx, dy = 2 z~/fy at the centre, so
+#     N = (0, dy, dz_y) x (dx, 0, dz_x) = (dy dz_x, dx dz_y, -dx dy), then
+#     normalized (camera frame; it faces the camera, N_z < 0);
+#   * a rendered pixel carries the normalized sum of its winning triangle's
+#     three vertex normals (flat over the triangle), turned towards the
+#     camera; triangles of class FU (skirts at discontinuities and at the
+#     range limit) are not surfaces to align to;
+#   * the cost of Sec. V step 5, C = sum |Z_M - Z_1|, is summed over the
+#     associated pixels.
+
+def downsample(depth, factor=2, z_max=8.0):
+    """Every ``factor``-th pixel of every ``factor``-th row; NaN where the
+    depth is not finite, not positive or beyond ``z_max``."""
+    d = np.asarray(depth, np.float32)[::factor, ::factor].copy()
+    with np.errstate(invalid="ignore"):
+        bad = ~(np.isfinite(d) & (d > 0) & (d <= np.float32(z_max)))
+    d[bad] = np.nan
+    return d
+
+
+def downsample_camera(cam, factor=2):
+    """Intrinsics of the downsampled image: pixel (u', v') is (factor u', factor v')."""
+    from dataclasses import replace
+    H = -(-cam.height // factor)
+    W = -(-cam.width // factor)
+    return replace(cam, fx=cam.fx / factor, fy=cam.fy / factor, cx=cam.cx / factor, cy=cam.cy / factor,
+                   width=W, height=H)
+
+
+def gaussian_weights(sigma, radius):
+    """1-D Gaussian weights over offsets -radius..radius, summing to 1."""
+    k = np.arange(-radius, radius + 1, dtype=np.float64)
+    w = np.exp(-k * k / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def smooth_depth(depth, sigma=1.0, radius=2):
+    """Gaussian smoothing of a depth image over its valid pixels: at a valid
+    centre, sum w_i w_j z / sum w_i w_j over the valid pixels of the window."""
+    z = np.asarray(depth, np.float64)
+    H, W = z.shape
+    w = gaussian_weights(sigma, radius)
+    num = np.zeros((H, W)); den = np.zeros((H, W))
+    valid = np.isfinite(z)
+    zp = np.pad(np.where(valid, z, 0.0), radius)
+    vp = np.pad(valid.astype(np.float64), radius)
+    for i in range(2 * radius + 1):
+        for j in range(2 * radius + 1):
+            wij = w[i] * w[j]
+            num += wij * zp[i:i + H, j:j + W]
+            den += wij * vp[i:i + H, j:j + W]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(valid, num / den, np.nan)
+
+
+def depth_normals(depth, cam, sigma=1.0, radius=2):
+    """Camera-frame unit normals [H,W,3] of a depth image by Eq. (2) (see the
+    readings above); NaN at the border and where the centre or one of its
+    four difference neighbours is invalid."""
+    zs = smooth_depth(depth, sigma, radius)
+    H, W = zs.shape
+    N = np.full((H, W, 3), np.nan)
+    c = zs[1:-1, 1:-1]
+    dzx = zs[1:-1, 2:] - zs[1:-1, :-2]
+    dzy = zs[2:, 1:-1] - zs[:-2, 1:-1]
+    dx = 2.0 * c / np.float64(np.float32(cam.fx))
+    dy = 2.0 * c / np.float64(np.float32(cam.fy))
+    n = np.stack([dy * dzx, dx * dzy, -dx * dy], -1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        n = n / np.linalg.norm(n, axis=-1, keepdims=True)
+    N[1:-1, 1:-1] = n
+    return N
+
+
+def vertex_normals(normals, stride, T_wc):
+    """World-frame normal of each meshify node (row-major over the node grid):
+    the normal image at the node's pixel (i stride, j stride), rotated by the
+    view's rotation.  NaN where the normal is undefined."""
+    n = np.asarray(normals, np.float64)[::stride, ::stride].reshape(-1, 3)
+    R = np.asarray(T_wc, np.float64).reshape(3, 4)[:, :3]
+    return n @ R.T
+
+
+def icp_terms(rend, mesh, vnormals, scan_d, scan_c, cam, T_wc, tol):
+    """Per-pixel projective association and point-to-plane terms.
+
+    A pixel is associated when the scan has a return there (class FO), the
+    pixel sees a map FO triangle whose three vertex normals are defined, and
+    |z_M - z_1| < tol for the rendered depth z_M and the scan depth z_1.
+    With n the camera-frame model normal turned towards the camera and
+    ray r: e = n . (P_1 - P_M) = (z_1 - z_M) (n . r), J = [n ; P_1 x n]
+    (the derivative under T_wc exp(delta) with the correspondence held)."""
+    pix = rend["pixels"]
+    ids = rend["id"]
+    hit = ids >= 0
+    tri = np.asarray(mesh[1])
+    cls = np.asarray(mesh[2])
+    idc = np.maximum(ids, 0)
+    vn = np.asarray(vnormals, np.float64)
+    s = vn[tri[idc, 0]] + vn[tri[idc, 1]] + vn[tri[idc, 2]]
+    R = np.asarray(T_wc, np.float64).reshape(3, 4)[:, :3]
+    nc = s @ R                                  # R^T s, row-wise
+    with np.errstate(invalid="ignore", divide="ignore"):
+        nc = nc / np.linalg.norm(nc, axis=-1, keepdims=True)
+    ray = rays(cam, pix)
+    ndr = (nc * ray).sum(-1)
+    nc = np.where((ndr < 0)[:, None], nc, -nc)
+    ndr = -np.abs(ndr)
+    z1 = np.asarray(scan_d, np.float64).reshape(-1)[pix]
+    c1 = np.asarray(scan_c).reshape(-1)[pix]
+    zM = rend["z"]
+    scan_pt = c1 == FO
+    model = scan_pt & hit & (cls[idc] == FO) & np.all(np.isfinite(nc), -1)
+    with np.errstate(invalid="ignore"):
+        dz = zM - z1
+        assoc = model & (np.abs(dz) < tol)
+    e = np.where(assoc, (z1 - np.where(assoc, zM, 0.0)) * ndr, 0.0)
+    P1 = np.where(assoc, z1, 0.0)[:, None] * ray
+    J = np.concatenate([nc, np.cross(P1, nc)], -1)
+    J = np.where(assoc[:, None], J, 0.0)
+    return dict(assoc=assoc, scan_pt=scan_pt, model=model, e=e, J=J, dz=dz, z1=z1, zM=zM, n=nc,
+                ray_norm=np.linalg.norm(ray, axis=-1))
+
+
+def icp_reduce(terms, mask=None):
+    """C = sum |z_M - z_1|, sum e^2, counts, b = sum e J, H = sum J^T J."""
+    m = np.ones(terms["e"].shape, bool) if mask is None else np.asarray(mask, bool)
+    a = terms["assoc"] & m
+    e = terms["e"][a]
+    J = terms["J"][a]
+    return dict(cost=float(np.abs(terms["dz"][a]).sum()), sse=float((e * e).sum()),
+                n_scan=int((terms["scan_pt"] & m).sum()), n_model=int((terms["model"] & m).sum()),
+                n_assoc=int(a.sum()), jtr=(e[:, None] * J).sum(0), jtj=J.T @ J,
+                grad=2.0 * (e[:, None] * J).sum(0))
+
+
+def icp_step(mesh, vnormals, cam, T_wc, scan_d, scan_c, tol, pixels=None, mode="contract"):
+    """One render, association and reduction of the point-to-plane ICP."""
+    rend = render(mesh, cam, T_wc, pixels, mode)
+    terms = icp_terms(rend, mesh, vnormals, scan_d, scan_c, cam, T_wc, tol)
+    out = icp_reduce(terms)
+    out["terms"] = terms
+    out["render"] = rend
+    return out
+
+
+def icp_tol_ties(terms, tol):
+    """Pixels whose association decision lies within the depth tolerance of tol."""
+    with np.errstate(invalid="ignore"):
+        scale = DEPTH_REL * np.fmax(np.abs(terms["zM"]), np.abs(terms["z1"]))
+        return terms["model"] & (np.abs(np.abs(terms["dz"]) - tol) <= scale)
