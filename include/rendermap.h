@@ -135,6 +135,29 @@ enum {
     RM_OUT_STRIDE = 48
 };
 
+/* Records of rm_icp_cost_grad use the same stride; its fields are
+ *   ICP_COST     C = sum over associated pixels of |Z_M - Z_1| (Sec. V, step 5)
+ *   ICP_SSE      sum over associated pixels of e_p^2
+ *   ICP_N_SCAN   scan pixels with a return (c_s = RM_FO)
+ *   ICP_N_MODEL  of those, pixels that see a map RM_FO triangle whose three
+ *                vertex normals are defined
+ *   N_ACTIVE     of those, associated pixels: |Z_M - Z_1| < tol
+ *   GRAD         d ICP_SSE / d delta = 2 sum e_p J_p
+ *   JTR, JTJ     b = sum e_p J_p, H = sum J_p^T J_p (upper triangle)
+ *   N_VISIBLE    as above
+ * with e_p = n . (P_1 - P_M) = (Z_1 - Z_M)(n . r), J_p = [n ; P_1 x n]: n is
+ * the normalized sum of the winning triangle's vertex normals in the camera
+ * frame, turned towards the camera; P_1 = Z_1 r and P_M = Z_M r are the scan
+ * and model points of the pixel; J_p is the derivative under T_wc exp(delta)
+ * with the correspondence held, as point-to-plane ICP linearizes.  The other
+ * fields are zero. */
+enum {
+    RM_OUT_ICP_COST = 0,
+    RM_OUT_ICP_SSE = 1,
+    RM_OUT_ICP_N_SCAN = 2,
+    RM_OUT_ICP_N_MODEL = 3
+};
+
 /* Maximum number of scans per rm_align_cost / rm_align_cost_grad call. */
 #define RM_MAX_SCANS 32
 
@@ -284,6 +307,58 @@ int rm_align_cost(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_
 int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
                        const int32_t* pose_off, const double* T_wc, rm_cost_params params,
                        double* out);
+
+/* ---------------------------------------------------------------- render-accelerated ICP (Sec. V) */
+
+/* Step 1 of the sequential depth-image alignment (Sec. V-B): keeps every
+ * factor-th pixel of every factor-th row and drops far points.
+ *   depth  device [H][W] f32; out device [ceil(H/factor)][ceil(W/factor)] f32
+ *   out(i, j) = depth(factor i, factor j) if it is a finite positive depth
+ *               of at most z_max, NaN otherwise.
+ * The downsampled image's camera has fx, fy, cx, cy divided by factor.
+ * factor >= 1; z_max > 0. */
+int rm_depth_downsample(rm_ctx* ctx, const float* depth, int32_t height, int32_t width, int32_t factor,
+                        float z_max, float* out);
+
+/* Depth-image normals of Eq. (2) (Sec. V-A).  The depth image is smoothed
+ * with a Gaussian (standard deviation sigma pixels, truncated to the
+ * (2 radius + 1)^2 window, weights renormalized over the window's valid
+ * pixels, FP64); with the central differences dz_x = z~(u+1, v) - z~(u-1, v),
+ * dz_y = z~(u, v+1) - z~(u, v-1) of the smoothed depth z~ and the metric
+ * steps dx = 2 z~/fx, dy = 2 z~/fy at the pixel, the normal is
+ *   N = (0, dy, dz_y) x (dx, 0, dz_x) = (dy dz_x, dx dz_y, -dx dy),
+ * normalized, in the camera frame (facing the camera: N_z < 0).
+ *   depth    device [H][W] f32, NaN = invalid
+ *   normals  device [H][W][3] f32; NaN on the image border and where the
+ *            pixel or one of its four difference neighbours is invalid.
+ * sigma > 0; radius in 0..RM_MAX_NORMAL_RADIUS.  Uses 8 H W bytes of the
+ * context's scratch. */
+#define RM_MAX_NORMAL_RADIUS 8
+int rm_depth_normals(rm_ctx* ctx, const float* depth, int32_t height, int32_t width, float fx, float fy,
+                     float sigma, int32_t radius, float* normals);
+
+/* World-frame normal of every vertex of rm_mesh_from_range's mesh of the
+ * same image with the same stride and pose: vertex i*gw + j takes the normal
+ * at pixel (j*stride, i*stride) rotated by T_wc's rotation (FP64, rounded
+ * to f32; NaN stays NaN).  This is how the rendered view of Sec. V-B step 3
+ * carries the normals of the depth image it was built from.
+ *   normals  device [H][W][3] f32 (rm_depth_normals)
+ *   T_wc     host, 12 doubles (row-major 3x4)
+ *   out      device [ceil(H/stride) * ceil(W/stride)][3] f32 */
+int rm_vertex_normals(rm_ctx* ctx, const float* normals, int32_t height, int32_t width, int32_t stride,
+                      const double* T_wc, float* out);
+
+/* Render-accelerated point-to-plane ICP (Sec. V): for every pose of S scans,
+ * renders the mesh, associates each scan return with the surface its pixel
+ * sees when their depths differ by less than tol (projective
+ * correspondence), and writes the cost, the point-to-plane residual sums and
+ * the Gauss-Newton blocks (RM_OUT_ICP_* and the fields listed there).
+ * vertex_normals: device [n_vertices][3] f32, world frame (rm_vertex_normals).
+ * Scans, pose_off, T_wc and out as for rm_align_cost_grad; the scan depth d_s
+ * of an RM_FO pixel is the point Z_1.  rm_gn_step on the records gives the
+ * ICP update.  tol > 0. */
+int rm_icp_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const float* vertex_normals, const rm_scan* scans,
+                     int32_t n_scans, const int32_t* pose_off, const double* T_wc, float tol, double* out);
 
 /* ---------------------------------------------------------------- optimizer step */
 

@@ -13,6 +13,14 @@ plain_align    -- the paper's optimizer for its own cost (Sec. IV-C): a
                   (one rm_align_cost launch for a single pose) per evaluation.
 batched_plain_align -- the same optimizer for many alignments in lockstep,
                   one launch per round of evaluations over all of them.
+icp_align      -- render-accelerated point-to-plane ICP (Sec. V): per
+                  iteration one rm_icp_cost_grad launch over all poses
+                  (render, projective association, point-to-plane blocks) and
+                  the on-device Levenberg-Marquardt update.
+sequential_depth_alignment -- Sec. V-B over a sequence of depth images: the
+                  relative pose of every consecutive pair, all pairs solved in
+                  the same launches (each pair's model placed at its own
+                  offset in space so that frustum culling keeps them apart).
 
 Pose increments x = (upsilon, omega) are applied on the right, T exp(x).
 """
@@ -307,3 +315,66 @@ def pose_errors(T, T_true):
     Rrel = np.einsum("kji,jl->kil", T[:, :, :3], Tt[:, :3])
     ang = np.arccos(np.clip((np.trace(Rrel, axis1=1, axis2=2) - 1) / 2, -1, 1))
     return dt, ang
+
+
+# ---------------------------------------------------------------------------- render-accelerated ICP (Sec. V)
+
+def icp_align(mesh, vnormals, scans, T0, tol=0.1, iters=10, lam=1e-6, poses_per_scan=None):
+    """Point-to-plane ICP with projective association for every pose at once.
+    Returns (T [P,3,4] f64 device, last result records [P,48])."""
+    T = R._poses(T0, mesh.xyz.device).clone()
+    out = torch.empty((T.shape[0], R.OUT_STRIDE), dtype=torch.float64, device=T.device)
+    for _ in range(iters):
+        R.icp_cost_grad(mesh, scans, T, vnormals, tol, poses_per_scan, out)
+        R.gn_step(out, T, lam)
+    return T.view(-1, 3, 4), out
+
+
+def _pair_offset(k, spacing):
+    """Translation placing pair k's model at its own spot of a 4 x 4 x n grid."""
+    return np.array([(k % 4) * spacing, ((k // 4) % 4) * spacing, (k // 16) * spacing], np.float64)
+
+
+def sequential_depth_alignment(depths, cam, factor=2, z_min=0.1, z_max=8.0, stride=1, max_edge=0.1,
+                               sigma=1.0, radius=2, tol=0.1, iters=10, lam=1e-6, spacing=50.0, init=None):
+    """Relative poses between consecutive depth images (Sec. V-B).
+
+    depths: list of device [H, W] f32 depth images of camera ``cam``.
+    For each pair (i, i+1): downsample both by ``factor`` dropping points
+    beyond z_max (step 1), normals of image i by Eq. (2) (step 2), its mesh
+    carrying those normals rendered from the current estimate of image i+1's
+    pose (step 3), point-to-plane ICP of image i+1's points (step 4),
+    repeated ``iters`` times (step 5).  ``init``: optional [N-1, 3, 4] initial
+    relative poses (identity otherwise).  Returns ([N-1, 3, 4] numpy relative
+    poses T_{i,i+1} (frame i+1 in frame i), last result records)."""
+    dev = depths[0].device
+    cam2 = R.downsample_camera(cam, factor)
+    ds = [R.depth_downsample(d, factor, z_max) for d in depths]
+    n_pairs = len(ds) - 1
+    T_all, outs = [], []
+    for b0 in range(0, n_pairs, R.MAX_SCANS):
+        ks = range(b0, min(b0 + R.MAX_SCANS, n_pairs))
+        meshes, vns, offs = [], [], []
+        for k in ks:
+            To = np.zeros((3, 4))
+            To[:, :3] = np.eye(3)
+            To[:, 3] = _pair_offset(k - b0, spacing)
+            offs.append(To)
+            meshes.append(R.mesh_from_range(ds[k], cam2, To, stride, z_min, z_max, max_edge, 0))
+            vns.append(R.vertex_normals(R.depth_normals(ds[k], cam2, sigma, radius), stride, To))
+        mesh = R.Mesh.concat(meshes).prepare()
+        vn = torch.cat(vns).contiguous()
+        scans = [R.scan_image(ds[k + 1], z_min, z_max, cam=cam2) for k in ks]
+        T0 = np.stack(offs)
+        if init is not None:
+            T0 = np.stack([np.vstack([o, [0, 0, 0, 1]]) @ np.vstack([np.asarray(init[k]), [0, 0, 0, 1]])
+                           for o, k in zip(offs, ks)])[:, :3]
+        T, out = icp_align(mesh, vn, scans, torch.from_numpy(np.ascontiguousarray(T0.reshape(-1, 12))).to(dev),
+                           tol, iters, lam, [1] * len(ks))
+        Tn = T.cpu().numpy()
+        for j, k in enumerate(ks):
+            Trel = Tn[j].copy()
+            Trel[:, 3] -= offs[j][:, 3]
+            T_all.append(Trel)
+        outs.append(out)
+    return np.stack(T_all), torch.cat(outs)

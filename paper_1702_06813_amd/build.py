@@ -9,7 +9,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "librendermap.so"
-SOURCES = ["rm_api.cpp", "rm_mesh.hip", "rm_raster.hip", "rm_optim.hip"]
+SOURCES = ["rm_api.cpp", "rm_mesh.hip", "rm_raster.hip", "rm_optim.hip", "rm_icp.hip"]
 
 # -ffp-contract=off: every float operation is the single IEEE operation
 # written (the rasterization contract uses explicit fmaf); packed FP32

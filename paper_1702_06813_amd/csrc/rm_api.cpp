@@ -193,7 +193,7 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
 // One scoring pass: cull, near-to-far cluster order, bin, rasterize (+ fused
 // comparison), reduce.
 int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
-             float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
+             float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out, const float* vnrm = nullptr) {
     plan(bd, tw, th);
     for (int s = 0; s < bd.n_scans; ++s)
         if (bd.s[s].tiles_x * bd.s[s].tiles_y > kMaxTiles || bd.s[s].tiles_x > 256 || bd.s[s].tiles_y > 256)
@@ -273,6 +273,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.n_order = (int32_t)R;
         a.rec = at<float>(ctx, o_rec);
         a.eps = eps;
+        a.vnrm = vnrm;
         a.depth_out = depth_out;
         a.tri_out = tri_out;
         a.cls_out = cls_out;
@@ -310,7 +311,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     RM_HIP(ctx, launch_raster(ctx->stream, bd, a, mode));
     if (pe1) RM_HIP(ctx, hipEventRecord(pe1, ctx->stream));
     if (mode != kRender)
-        RM_HIP(ctx, launch_reduce(ctx->stream, bd, a.rec, vis_tris, eps, mode == kGrad, out));
+        RM_HIP(ctx, launch_reduce(ctx->stream, bd, a.rec, vis_tris, eps, mode, out));
     if (!capturing(ctx) && !ctx->bin_pending) {
         if (!ctx->bin_ev) RM_HIP(ctx, hipEventCreateWithFlags(&ctx->bin_ev, hipEventDisableTiming));
         RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, bin_max, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -322,16 +323,16 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
 
 // Chooses the tile shape (explicit, cached autotune result, or default) and runs.
 int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const double* T_wc, float eps,
-               double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out) {
+               double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out, const float* vnrm = nullptr) {
     if (ctx->tile_w) return run_pass(ctx, mesh, bd, ctx->tile_w, ctx->tile_h, mode, T_wc, eps, out, depth_out,
-                                     tri_out, cls_out);
+                                     tri_out, cls_out, vnrm);
     const auto key = std::make_tuple(bd.s[0].width, bd.s[0].height, bd.n_poses, mesh->n_tris, mode);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end())
         return run_pass(ctx, mesh, bd, it->second.first, it->second.second, mode, T_wc, eps, out, depth_out,
-                        tri_out, cls_out);
+                        tri_out, cls_out, vnrm);
     if (!ctx->autotune || capturing(ctx))
-        return run_pass(ctx, mesh, bd, 64, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out);
+        return run_pass(ctx, mesh, bd, 64, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out, vnrm);
     if (!ctx->ev0) {
         RM_HIP(ctx, hipEventCreate(&ctx->ev0));
         RM_HIP(ctx, hipEventCreate(&ctx->ev1));
@@ -347,7 +348,7 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
                 RM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
             }
             int rc = run_pass(ctx, mesh, bd, kTiles[k][0], kTiles[k][1], mode, T_wc, eps, out, depth_out, tri_out,
-                              cls_out);
+                              cls_out, vnrm);
             if (rc) return rc;
         }
         RM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -358,7 +359,7 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
         else if (ms > 1.25f * best) break;
     }
     ctx->tuned[key] = {kTiles[bi][0], kTiles[bi][1]};
-    return run_pass(ctx, mesh, bd, kTiles[bi][0], kTiles[bi][1], mode, T_wc, eps, out, depth_out, tri_out, cls_out);
+    return run_pass(ctx, mesh, bd, kTiles[bi][0], kTiles[bi][1], mode, T_wc, eps, out, depth_out, tri_out, cls_out, vnrm);
 }
 
 int fill_scan(rm_ctx* ctx, ScanDesc& d, const rm_camera& c) {
@@ -371,7 +372,7 @@ int fill_scan(rm_ctx* ctx, ScanDesc& d, const rm_camera& c) {
 }
 
 int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t S, const int32_t* pose_off,
-                 const double* T_wc, rm_cost_params params, double* out, int mode) {
+                 const double* T_wc, rm_cost_params params, double* out, int mode, const float* vnrm = nullptr) {
     if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
     ctx->err.clear();
     int rc = check_mesh(ctx, mesh);
@@ -403,7 +404,7 @@ int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t
     if (!T_wc || !out) return fail(ctx, RM_ERR_INVALID_ARG, "T_wc and out must be non-NULL");
     bd.n_poses = P;
     DeviceGuard g(ctx->device);
-    return run_scored(ctx, mesh, bd, mode, T_wc, params.eps, out, nullptr, nullptr, nullptr);
+    return run_scored(ctx, mesh, bd, mode, T_wc, params.eps, out, nullptr, nullptr, nullptr, vnrm);
 }
 
 }  // namespace
@@ -653,6 +654,76 @@ int rm_align_cost(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_
 int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
                        const int32_t* pose_off, const double* T_wc, rm_cost_params params, double* out) {
     return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kGrad);
+}
+
+int rm_depth_downsample(rm_ctx* ctx, const float* depth, int32_t height, int32_t width, int32_t factor, float z_max,
+                        float* out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (!depth || !out) return fail(ctx, RM_ERR_INVALID_ARG, "NULL image pointer");
+    if (height < 1 || width < 1 || (int64_t)height * width > ((int64_t)1 << 26))
+        return fail(ctx, RM_ERR_INVALID_ARG, "bad image size %dx%d", width, height);
+    if (factor < 1 || factor > 64) return fail(ctx, RM_ERR_INVALID_ARG, "factor %d outside 1..64", factor);
+    if (!(z_max > 0.0f)) return fail(ctx, RM_ERR_INVALID_ARG, "z_max must be positive");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_downsample(ctx->stream, depth, height, width, factor, z_max, out));
+    return RM_OK;
+}
+
+int rm_depth_normals(rm_ctx* ctx, const float* depth, int32_t height, int32_t width, float fx, float fy, float sigma,
+                     int32_t radius, float* normals) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (!depth || !normals) return fail(ctx, RM_ERR_INVALID_ARG, "NULL image pointer");
+    if (height < 1 || width < 1 || (int64_t)height * width > ((int64_t)1 << 26))
+        return fail(ctx, RM_ERR_INVALID_ARG, "bad image size %dx%d", width, height);
+    if (!(fx > 0.0f) || !(fy > 0.0f) || !std::isfinite(fx) || !std::isfinite(fy))
+        return fail(ctx, RM_ERR_INVALID_ARG, "fx and fy must be positive and finite");
+    if (!(sigma > 0.0f) || !std::isfinite(sigma)) return fail(ctx, RM_ERR_INVALID_ARG, "sigma must be positive");
+    if (radius < 0 || radius > RM_MAX_NORMAL_RADIUS)
+        return fail(ctx, RM_ERR_INVALID_ARG, "radius %d outside 0..%d", radius, RM_MAX_NORMAL_RADIUS);
+    GaussW gw;
+    std::memset(&gw, 0, sizeof(gw));
+    gw.radius = radius;
+    double sum = 0.0;
+    for (int k = -radius; k <= radius; ++k) {
+        gw.w[k + radius] = std::exp(-(double)k * k / (2.0 * (double)sigma * (double)sigma));
+        sum += gw.w[k + radius];
+    }
+    for (int k = 0; k <= 2 * radius; ++k) gw.w[k] /= sum;
+    DeviceGuard g(ctx->device);
+    int rc = ensure_scratch(ctx, (size_t)height * width * sizeof(double));
+    if (rc) return rc;
+    RM_HIP(ctx, launch_depth_normals(ctx->stream, depth, height, width, (double)fx, (double)fy, gw, at<double>(ctx, 0),
+                                     normals));
+    return RM_OK;
+}
+
+int rm_vertex_normals(rm_ctx* ctx, const float* normals, int32_t height, int32_t width, int32_t stride,
+                      const double* T_wc, float* out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (!normals || !out || !T_wc) return fail(ctx, RM_ERR_INVALID_ARG, "NULL pointer");
+    if (height < 1 || width < 1 || (int64_t)height * width > ((int64_t)1 << 26))
+        return fail(ctx, RM_ERR_INVALID_ARG, "bad image size %dx%d", width, height);
+    if (stride < 1) return fail(ctx, RM_ERR_INVALID_ARG, "stride must be >= 1");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(T_wc[k])) return fail(ctx, RM_ERR_INVALID_ARG, "T_wc is not finite");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_vertex_normals(ctx->stream, normals, height, width, stride, T_wc, out));
+    return RM_OK;
+}
+
+int rm_icp_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const float* vertex_normals, const rm_scan* scans,
+                     int32_t n_scans, const int32_t* pose_off, const double* T_wc, float tol, double* out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (!vertex_normals) return fail(ctx, RM_ERR_INVALID_ARG, "vertex_normals is NULL");
+    if (!(tol > 0.0f) || !std::isfinite(tol)) return fail(ctx, RM_ERR_INVALID_ARG, "tol must be positive and finite");
+    rm_cost_params p;
+    p.eps = tol;
+    p.flags = 0;
+    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, p, out, kIcp, vertex_normals);
 }
 
 int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda, double* T_wc, double* delta_out) {

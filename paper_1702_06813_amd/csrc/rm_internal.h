@@ -46,7 +46,7 @@ struct BatchDesc {
     ScanDesc s[RM_MAX_SCANS];
 };
 
-enum Mode { kRender = 0, kCost = 1, kGrad = 2 };
+enum Mode { kRender = 0, kCost = 1, kGrad = 2, kIcp = 3 };
 
 struct RasterArgs {
     const float* xyz;
@@ -70,7 +70,8 @@ struct RasterArgs {
     int32_t* queue;              // device counter of taken items (persistent scheduling)
     int32_t n_order;
     float* rec;                  // partial records [n_records][kRecFields]
-    float eps;
+    float eps;                   // Table I threshold; the association tolerance in ICP mode
+    const float* vnrm;           // ICP mode: [n_vertices][3] world-frame vertex normals
     // render outputs
     float* depth_out;
     int32_t* tri_out;
@@ -103,7 +104,21 @@ hipError_t launch_order(hipStream_t st, const BatchDesc& bd, const int32_t* bin_
 // Workgroups of the persistent rasterizer that fit on the device at once.
 int persistent_grid(int tile_w, int tile_h, int mode);
 hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec,
-                         const int32_t* vis_tris, float eps, int grad, double* out);
+                         const int32_t* vis_tris, float eps, int mode, double* out);
+
+// Gaussian weights over offsets -radius..radius (summing to 1).
+struct GaussW {
+    double w[2 * RM_MAX_NORMAL_RADIUS + 1];
+    int32_t radius;
+};
+hipError_t launch_downsample(hipStream_t st, const float* depth, int32_t H, int32_t W, int32_t f, float z_max,
+                             float* out);
+// smoothed: device scratch [H][W] f64
+hipError_t launch_depth_normals(hipStream_t st, const float* depth, int32_t H, int32_t W, double fx, double fy,
+                                const GaussW& g, double* smoothed, float* normals);
+// T_wc: host, 12 doubles
+hipError_t launch_vertex_normals(hipStream_t st, const float* normals, int32_t H, int32_t W, int32_t stride,
+                                 const double* T_wc, float* out);
 hipError_t launch_gn_step(hipStream_t st, const double* out, int32_t P, double lambda, double* T,
                           double* delta_out);
 hipError_t launch_adam_step(hipStream_t st, const double* out, int32_t P, double lr, double b1, double b2,

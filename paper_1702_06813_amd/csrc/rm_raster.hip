@@ -672,9 +672,10 @@ struct Acc {
     int e_table;
     int cnt[9];
     int n_active;
-    float e_soft;
+    float e_soft;          // ICP mode: the cost sum |Z_M - Z_1| of the associated pixels
     float jtr[6];
     float jtj[21];
+    float sse;             // ICP mode: sum of squared point-to-plane residuals
 };
 
 // Table I cell of a pixel and its value: returns the cell (0..8) and sets s.
@@ -818,7 +819,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
 
     // ---------------------------------------------------------------- resolve
     Acc acc;
-    acc.e_table = 0; acc.n_active = 0; acc.e_soft = 0.0f;
+    acc.e_table = 0; acc.n_active = 0; acc.e_soft = 0.0f; acc.sse = 0.0f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc.cnt[k] = 0;
 #pragma unroll
@@ -848,6 +849,51 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         const int c_s = sd.cls[pix];
         const float d_s = sd.depth[pix];
         const float dz = z - d_s;
+        if (MODE == kIcp) {
+            // Projective association (Sec. V): a scan return and the map FO
+            // surface the pixel sees, whose depths differ by less than the
+            // tolerance.  The model normal is the normalized sum of the
+            // winner's vertex normals, in the camera frame, facing the camera.
+            if (c_s != RM_FO) continue;
+            acc.cnt[0] += 1;
+            if (c_r != RM_FO) continue;
+            const int32_t* tv = a.tri + 3 * (int64_t)id;
+            const float* n0 = a.vnrm + 3 * (int64_t)min((uint32_t)tv[0], a.vmax);
+            const float* n1 = a.vnrm + 3 * (int64_t)min((uint32_t)tv[1], a.vmax);
+            const float* n2 = a.vnrm + 3 * (int64_t)min((uint32_t)tv[2], a.vmax);
+            const float w0 = (n0[0] + n1[0]) + n2[0], w1 = (n0[1] + n1[1]) + n2[1], w2 = (n0[2] + n1[2]) + n2[2];
+            float nx = fmaf(P.R[0][2], w2, fmaf(P.R[0][1], w1, P.R[0][0] * w0));
+            float ny = fmaf(P.R[1][2], w2, fmaf(P.R[1][1], w1, P.R[1][0] * w0));
+            float nz = fmaf(P.R[2][2], w2, fmaf(P.R[2][1], w1, P.R[2][0] * w0));
+            const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+            if (!(nn > 0.0f) || isinf(nn)) continue;                // a vertex normal is undefined
+            acc.cnt[1] += 1;
+            if (!(fabsf(dz) < a.eps)) continue;
+            const float inv = 1.0f / sqrtf(nn);
+            nx *= inv; ny *= inv; nz *= inv;
+            const float rx = ((float)x - cam.cx) * ifx, ry = ((float)y - cam.cy) * ify;
+            float ndr = fmaf(nx, rx, fmaf(ny, ry, nz));
+            if (!(ndr < 0.0f)) { nx = -nx; ny = -ny; nz = -nz; ndr = -ndr; }
+            // e = n . (P_1 - P_M) = (z_1 - z_M)(n . r); J = [n ; P_1 x n]
+            const float e = (d_s - z) * ndr;
+            const float Px = d_s * rx, Py = d_s * ry, Pz = d_s;
+            float J[6];
+            J[0] = nx; J[1] = ny; J[2] = nz;
+            J[3] = Py * nz - Pz * ny;
+            J[4] = Pz * nx - Px * nz;
+            J[5] = Px * ny - Py * nx;
+            acc.n_active += 1;
+            acc.e_soft += fabsf(dz);
+            acc.sse = fmaf(e, e, acc.sse);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) acc.jtr[i] = fmaf(e, J[i], acc.jtr[i]);
+            int k = 0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = i; j < 6; ++j) { acc.jtj[k] = fmaf(J[i], J[j], acc.jtj[k]); ++k; }
+            continue;
+        }
         int s;
         const int cell = table1(c_r, c_s, dz, eps, s);
         acc.e_table += s;
@@ -894,19 +940,20 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     if (MODE == kRender) return;
 
     // ---------------------------------------------------------------- reduction (fixed order)
-    constexpr int NF = MODE == kGrad ? 39 : 12;
+    constexpr int NF = MODE == kIcp ? 40 : (MODE == kGrad ? 39 : 12);
     float v[NF];
     v[0] = __int_as_float(acc.e_table);
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[1 + k] = __int_as_float(acc.cnt[k]);
     v[10] = __int_as_float(acc.n_active);
     v[11] = acc.e_soft;
-    if (MODE == kGrad) {
+    if (MODE == kGrad || MODE == kIcp) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) v[12 + k] = acc.jtr[k];
 #pragma unroll
         for (int k = 0; k < 21; ++k) v[18 + k] = acc.jtj[k];
     }
+    if (MODE == kIcp) v[39] = acc.sse;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         if (f <= 10) {
@@ -1145,7 +1192,7 @@ constexpr int kRedSplit = 8;
 
 __global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd, const float* __restrict__ rec,
                                                                    const int32_t* __restrict__ vis_tris, float eps,
-                                                                   int grad, double* __restrict__ out) {
+                                                                   int mode, double* __restrict__ out) {
     __shared__ double part[kRedSplit][kRecFields];
     __shared__ double val[kRecFields];
     const int pose = blockIdx.x;
@@ -1173,7 +1220,21 @@ __global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd,
     __syncthreads();
     double* o = out + (int64_t)pose * RM_OUT_STRIDE;
     const int g = threadIdx.x;
-    if (g < RM_OUT_STRIDE) {
+    const bool grad = mode == kGrad;
+    if (mode == kIcp && g < RM_OUT_STRIDE) {
+        // ICP records: cost, sum of squared residuals, counts, blocks
+        double x = 0.0;
+        if (g == RM_OUT_ICP_COST) x = val[11];
+        else if (g == RM_OUT_ICP_SSE) x = val[39];
+        else if (g == RM_OUT_ICP_N_SCAN) x = val[1];
+        else if (g == RM_OUT_ICP_N_MODEL) x = val[2];
+        else if (g == RM_OUT_N_ACTIVE) x = val[10];
+        else if (g >= RM_OUT_GRAD && g < RM_OUT_GRAD + 6) x = 2.0 * val[12 + g - RM_OUT_GRAD];
+        else if (g >= RM_OUT_JTR && g < RM_OUT_JTR + 6) x = val[12 + g - RM_OUT_JTR];
+        else if (g >= RM_OUT_JTJ && g < RM_OUT_JTJ + 21) x = val[18 + g - RM_OUT_JTJ];
+        else if (g == RM_OUT_N_VISIBLE) x = (double)vis_tris[pose];
+        o[g] = x;
+    } else if (g < RM_OUT_STRIDE) {
         double x = 0.0;
         if (g == RM_OUT_E_TABLE) x = val[0];
         else if (g == RM_OUT_E_SOFT) x = val[11];
@@ -1263,6 +1324,7 @@ hipError_t launch_raster_t(hipStream_t st, const BatchDesc& bd, const RasterArgs
                             : (unsigned)(chunk * 8));
     if (mode == kRender) hipLaunchKernelGGL((k_raster<TW, TH, kRender>), grid, dim3(kWG), 0, st, bd, a);
     else if (mode == kCost) hipLaunchKernelGGL((k_raster<TW, TH, kCost>), grid, dim3(kWG), 0, st, bd, a);
+    else if (mode == kIcp) hipLaunchKernelGGL((k_raster<TW, TH, kIcp>), grid, dim3(kWG), 0, st, bd, a);
     else hipLaunchKernelGGL((k_raster<TW, TH, kGrad>), grid, dim3(kWG), 0, st, bd, a);
     return hipGetLastError();
 }
@@ -1321,7 +1383,9 @@ int resident_blocks() {
 template <int TW, int TH>
 int resident_t(int mode) {
     return mode == kRender ? resident_blocks<TW, TH, kRender>()
-                           : (mode == kCost ? resident_blocks<TW, TH, kCost>() : resident_blocks<TW, TH, kGrad>());
+                           : (mode == kCost ? resident_blocks<TW, TH, kCost>()
+                                            : (mode == kIcp ? resident_blocks<TW, TH, kIcp>()
+                                                            : resident_blocks<TW, TH, kGrad>()));
 }
 }  // namespace
 
@@ -1339,10 +1403,10 @@ hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& 
 }
 
 hipError_t launch_reduce(hipStream_t st, const BatchDesc& bd, const float* rec, const int32_t* vis_tris,
-                         float eps, int grad, double* out) {
+                         float eps, int mode, double* out) {
     if (bd.n_poses == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)bd.n_poses), dim3(kRecFields * kRedSplit), 0, st, bd, rec, vis_tris,
-                       eps, grad, out);
+                       eps, mode, out);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ RM_OK, RM_ERR_INVALID_ARG, RM_ERR_OOM, RM_ERR_DEVICE, RM_ERR_CAPACITY, RM_ERR_UN
 FO, FU, UO, NONE = 0, 1, 2, 3
 OUT_E_TABLE, OUT_E_SOFT, OUT_COUNTS, OUT_N_ACTIVE = 0, 1, 2, 11
 OUT_GRAD, OUT_JTR, OUT_JTJ, OUT_N_VISIBLE, OUT_STRIDE = 12, 18, 24, 45, 48
+OUT_ICP_COST, OUT_ICP_SSE, OUT_ICP_N_SCAN, OUT_ICP_N_MODEL = 0, 1, 2, 3
+MAX_NORMAL_RADIUS = 8
 MAX_SCANS = 32
 CLUSTER_TRIS = 256
 
@@ -28,7 +30,8 @@ ABI_SYMBOLS = [
     "rm_ctx_create", "rm_ctx_destroy", "rm_ctx_set_stream", "rm_last_error", "rm_set_tile", "rm_autotune",
     "rm_get_tile", "rm_set_schedule", "rm_profile", "rm_profile_read", "rm_graph_begin", "rm_graph_end", "rm_graph_launch", "rm_graph_destroy", "rm_scan_image",
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
-    "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract",
+    "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract", "rm_depth_downsample",
+    "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad",
 ]
 
 
@@ -96,6 +99,10 @@ def load_library(path: Path | str | None = None):
             "rm_gn_step": [V, V, I32, D, V, V],
             "rm_adam_step": [V, V, I32, D, D, D, I32, V, V, V],
             "rm_se3_retract": [V, V, V, I32, V],
+            "rm_depth_downsample": [V, V, I32, I32, I32, F, V],
+            "rm_depth_normals": [V, V, I32, I32, F, F, F, I32, V],
+            "rm_vertex_normals": [V, V, I32, I32, I32, V, V],
+            "rm_icp_cost_grad": [V, ctypes.POINTER(CMesh), V, ctypes.POINTER(CScan), I32, V, V, F, V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -482,3 +489,72 @@ class AlignCost(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         return grad_out[:, None] * g, None, None, None, None
+
+
+# ---------------------------------------------------------------------------- render-accelerated ICP (Sec. V)
+
+def downsample_camera(cam, factor: int = 2):
+    """Intrinsics of rm_depth_downsample's output: pixel (u', v') is (factor u', factor v')."""
+    from dataclasses import replace
+    return replace(cam, fx=cam.fx / factor, fy=cam.fy / factor, cx=cam.cx / factor, cy=cam.cy / factor,
+                   width=-(-int(cam.width) // factor), height=-(-int(cam.height) // factor))
+
+
+def depth_downsample(depth: torch.Tensor, factor: int = 2, z_max: float = 8.0) -> torch.Tensor:
+    """rm_depth_downsample: every factor-th pixel of every factor-th row, NaN
+    where not a finite positive depth up to z_max."""
+    _need(depth, torch.float32, "depth", None)
+    H, W = depth.shape
+    out = torch.empty((-(-H // factor), -(-W // factor)), dtype=torch.float32, device=depth.device)
+    context(depth.device).call("rm_depth_downsample", _ptr(depth), H, W, factor, z_max, _ptr(out))
+    return out
+
+
+def depth_normals(depth: torch.Tensor, cam, sigma: float = 1.0, radius: int = 2) -> torch.Tensor:
+    """rm_depth_normals: camera-frame unit normals [H, W, 3] of Eq. (2)."""
+    _need(depth, torch.float32, "depth", None)
+    H, W = depth.shape
+    if (H, W) != (int(cam.height), int(cam.width)):
+        raise ValueError("depth must match the camera")
+    out = torch.empty((H, W, 3), dtype=torch.float32, device=depth.device)
+    context(depth.device).call("rm_depth_normals", _ptr(depth), H, W, float(cam.fx), float(cam.fy), sigma, radius,
+                               _ptr(out))
+    return out
+
+
+def vertex_normals(normals: torch.Tensor, stride: int, T_wc) -> torch.Tensor:
+    """rm_vertex_normals: world-frame normal of every vertex of the
+    rm_mesh_from_range mesh of the same image, stride and pose."""
+    _need(normals, torch.float32, "normals", None)
+    H, W, _ = normals.shape
+    out = torch.empty((-(-H // stride) * -(-W // stride), 3), dtype=torch.float32, device=normals.device)
+    keep, pp = _pose_host(T_wc)
+    context(normals.device).call("rm_vertex_normals", _ptr(normals), H, W, stride, pp, _ptr(out))
+    return out
+
+
+def icp_cost_grad(mesh, scans, T_wc, vertex_normals: torch.Tensor, tol: float = 0.1, poses_per_scan=None,
+                  out=None):
+    """rm_icp_cost_grad: [P, 48] ICP records (OUT_ICP_* and the JTR/JTJ blocks)."""
+    dev = mesh.xyz.device
+    _need(vertex_normals, torch.float32, "vertex_normals", dev)
+    if tuple(vertex_normals.shape) != (mesh.xyz.shape[0], 3):
+        raise ValueError("vertex_normals must be [n_vertices, 3]")
+    if isinstance(scans, Scan):
+        scans = [scans]
+    if poses_per_scan is None:
+        poses_per_scan = [T_wc.reshape(-1, 12).shape[0]]
+    arr, offs, P = _scan_args(scans, poses_per_scan)
+    T = _poses(T_wc, dev)
+    if T.shape[0] != P:
+        raise ValueError(f"{T.shape[0]} poses given, pose counts sum to {P}")
+    if out is None:
+        out = torch.empty((P, OUT_STRIDE), dtype=torch.float64, device=dev)
+    else:
+        _need(out, torch.float64, "out", dev)
+        if tuple(out.shape) != (P, OUT_STRIDE):
+            raise ValueError("out must be [P, 48]")
+    m = mesh.struct()
+    context(dev).call("rm_icp_cost_grad", ctypes.byref(m), _ptr(vertex_normals), arr, len(scans),
+                      ctypes.cast(offs, ctypes.c_void_p), _ptr(T), float(tol), _ptr(out))
+    return out

@@ -164,3 +164,42 @@ def uneven(seed: int = 5, n_views: int = 56, n_scans: int = 32) -> Stream:
         poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n)])
         scans.append(StreamScan(cam, T, depth, poses))
     return Stream("uneven", scene, S.QVGA, views, depths, scans)
+
+
+@dataclass
+class Sequence:
+    """A sensor moving through a scene: ground-truth poses and range images,
+    for the sequential depth-image alignment of Sec. V-B."""
+    name: str
+    cam: S.Camera
+    scene: S.Scene
+    poses: np.ndarray                  # [N,3,4] ground truth
+    depths: list                       # N [H,W] f32 range images
+    z_min: float = 0.1
+    z_max: float = 8.0
+
+
+def odometry(seed: int = 9, n_frames: int = 33, step: float = 0.03, noise_rel: float = 0.005,
+             dropout: float = 0.02, cam: S.Camera | None = None) -> Sequence:
+    """Kinect-like 640x480 frames along an arc at 75% of the half extents of
+    a 6x5x2.8 m room with 16 boxes, each frame looking across the room:
+    consecutive frames ``step`` metres apart (~1 degree of yaw), with a slow
+    height and pitch wave; multiplicative range noise and i.i.d. dropouts."""
+    rng = np.random.default_rng(seed)
+    cam = S.KINECT if cam is None else cam
+    scene = S.random_box_room(seed, (6.0, 5.0, 2.8), 16)
+    c = _room_center(scene)
+    half = 0.5 * (scene.room_hi - scene.room_lo)
+    a, b = 0.75 * half[0], 0.75 * half[1]
+    ang0 = rng.uniform(0, 2 * np.pi)
+    poses, depths = [], []
+    ang = ang0
+    for k in range(n_frames):
+        pos = np.array([c[0] + a * np.cos(ang), c[1] + b * np.sin(ang), 1.4 + 0.1 * np.sin(0.2 * k)])
+        yaw = np.arctan2(c[1] - pos[1], c[0] - pos[0]) + 0.2 * np.sin(0.05 * k)
+        T = S.look_pose(pos, yaw, np.deg2rad(-20.0 + 5.0 * np.sin(0.13 * k)))
+        poses.append(T)
+        depths.append(S.range_image(scene, cam, T, seed * 1000 + k, noise_rel=noise_rel, dropout=dropout))
+        # arc length per step: the ellipse's speed at this angle
+        ang += step / np.hypot(a * np.sin(ang), b * np.cos(ang))
+    return Sequence("odometry", cam, scene, np.stack(poses), depths)
