@@ -335,6 +335,34 @@ def _pair_offset(k, spacing):
     return np.array([(k % 4) * spacing, ((k // 4) % 4) * spacing, (k // 16) * spacing], np.float64)
 
 
+def prepare_pairs(depths, cam, ks, factor=2, z_min=0.1, z_max=8.0, stride=1, max_edge=0.1, sigma=1.0, radius=2,
+                  spacing=50.0, ds=None):
+    """Steps 1-2 of Sec. V-B for the consecutive pairs (k, k+1), k in ``ks``
+    (at most MAX_SCANS): the model of each pair is the mesh of downsampled
+    image k, placed at its own offset and carrying its Eq. (2) normals; the
+    scan is downsampled image k+1.  Returns (mesh, vertex normals, scans,
+    offset poses [n,3,4], downsampled camera)."""
+    cam2 = R.downsample_camera(cam, factor)
+    if ds is None:
+        ds = {}
+    for k in ks:
+        for j in (k, k + 1):
+            if j not in ds:
+                ds[j] = R.depth_downsample(depths[j], factor, z_max)
+    meshes, vns, offs = [], [], []
+    for i, k in enumerate(ks):
+        To = np.zeros((3, 4))
+        To[:, :3] = np.eye(3)
+        To[:, 3] = _pair_offset(i, spacing)
+        offs.append(To)
+        meshes.append(R.mesh_from_range(ds[k], cam2, To, stride, z_min, z_max, max_edge, 0))
+        vns.append(R.vertex_normals(R.depth_normals(ds[k], cam2, sigma, radius), stride, To))
+    mesh = R.Mesh.concat(meshes).prepare()
+    vn = torch.cat(vns).contiguous()
+    scans = [R.scan_image(ds[k + 1], z_min, z_max, cam=cam2) for k in ks]
+    return mesh, vn, scans, np.stack(offs), cam2
+
+
 def sequential_depth_alignment(depths, cam, factor=2, z_min=0.1, z_max=8.0, stride=1, max_edge=0.1,
                                sigma=1.0, radius=2, tol=0.1, iters=10, lam=1e-6, spacing=50.0, init=None):
     """Relative poses between consecutive depth images (Sec. V-B).
@@ -348,31 +376,20 @@ def sequential_depth_alignment(depths, cam, factor=2, z_min=0.1, z_max=8.0, stri
     relative poses (identity otherwise).  Returns ([N-1, 3, 4] numpy relative
     poses T_{i,i+1} (frame i+1 in frame i), last result records)."""
     dev = depths[0].device
-    cam2 = R.downsample_camera(cam, factor)
-    ds = [R.depth_downsample(d, factor, z_max) for d in depths]
-    n_pairs = len(ds) - 1
-    T_all, outs = [], []
+    n_pairs = len(depths) - 1
+    T_all, outs, ds = [], [], {}
     for b0 in range(0, n_pairs, R.MAX_SCANS):
-        ks = range(b0, min(b0 + R.MAX_SCANS, n_pairs))
-        meshes, vns, offs = [], [], []
-        for k in ks:
-            To = np.zeros((3, 4))
-            To[:, :3] = np.eye(3)
-            To[:, 3] = _pair_offset(k - b0, spacing)
-            offs.append(To)
-            meshes.append(R.mesh_from_range(ds[k], cam2, To, stride, z_min, z_max, max_edge, 0))
-            vns.append(R.vertex_normals(R.depth_normals(ds[k], cam2, sigma, radius), stride, To))
-        mesh = R.Mesh.concat(meshes).prepare()
-        vn = torch.cat(vns).contiguous()
-        scans = [R.scan_image(ds[k + 1], z_min, z_max, cam=cam2) for k in ks]
-        T0 = np.stack(offs)
+        ks = list(range(b0, min(b0 + R.MAX_SCANS, n_pairs)))
+        mesh, vn, scans, offs, _ = prepare_pairs(depths, cam, ks, factor, z_min, z_max, stride, max_edge, sigma,
+                                                 radius, spacing, ds)
+        T0 = offs.copy()
         if init is not None:
             T0 = np.stack([np.vstack([o, [0, 0, 0, 1]]) @ np.vstack([np.asarray(init[k]), [0, 0, 0, 1]])
                            for o, k in zip(offs, ks)])[:, :3]
         T, out = icp_align(mesh, vn, scans, torch.from_numpy(np.ascontiguousarray(T0.reshape(-1, 12))).to(dev),
                            tol, iters, lam, [1] * len(ks))
         Tn = T.cpu().numpy()
-        for j, k in enumerate(ks):
+        for j in range(len(ks)):
             Trel = Tn[j].copy()
             Trel[:, 3] -= offs[j][:, 3]
             T_all.append(Trel)
