@@ -199,3 +199,51 @@ def test_sequential_depth_alignment_recovers_motion(rm):
         assert dt[0] < 5e-3 and np.rad2deg(ang[0]) < 0.25, (k, dt[0], np.rad2deg(ang[0]))
     o = out.cpu().numpy()
     assert (o[:, 11] > 10000).all()               # associated pixels per pair at 320x240
+
+
+@pytest.mark.slow
+def test_icp_full_batch_sampled(rm):
+    """The benchmark's launch: 32 consecutive pairs of the 33-frame sequence
+    at 320x240, every pair's model (built by the oracle) at its own offset,
+    4.5M triangles, 32 scans in one launch.  Three pairs are checked on 1500
+    sampled pixels each (scan masks) against the oracle rendering the whole
+    mesh; all 32 rows of the launch equal single-scan launches."""
+    _say("icp full batch (32 pairs, 4.5M triangles)")
+    from paper_1702_06813_amd import align
+    seq = configs.odometry(n_frames=33)
+    cam2 = O.downsample_camera(seq.cam, 2)
+    ds = [O.downsample(d, 2, 8.0) for d in seq.depths]
+    xyz, tri, cls, vns, offs, off = [], [], [], [], [], 0
+    for k in range(32):
+        To = np.zeros((3, 4)); To[:, :3] = np.eye(3); To[:, 3] = align._pair_offset(k, 50.0)
+        v, t, c = O.meshify(ds[k], cam2, To, 1, 0.1, 8.0, 0.1)
+        xyz.append(v); tri.append(t + off); cls.append(c); off += len(v)
+        vns.append(O.vertex_normals(O.depth_normals(ds[k], cam2), 1, To).astype(np.float32))
+        offs.append(To)
+    mesh = (np.concatenate(xyz), np.concatenate(tri).astype(np.int32), np.concatenate(cls))
+    vn = np.concatenate(vns)
+    assert mesh[1].shape[0] > 4_000_000
+    dm = rm.Mesh.from_arrays(*mesh, device=DEV).prepare()
+    vnd = torch.from_numpy(vn).to(DEV)
+    scans = [rm.scan_image(torch.from_numpy(ds[k + 1]).to(DEV), 0.1, 8.0, cam=cam2) for k in range(32)]
+    rng = np.random.default_rng(24)
+    poses = [S.perturb(offs[k], rng, 0.01, np.deg2rad(0.5)) for k in range(32)]
+    T = _T(poses)
+    allr = rm.icp_cost_grad(dm, scans, T, vnd, TOL, poses_per_scan=[1] * 32).cpu().numpy()
+    for k in (0, 13, 31):
+        one = rm.icp_cost_grad(dm, scans[k], T[k:k + 1].contiguous(), vnd, TOL).cpu().numpy()
+        np.testing.assert_array_equal(one[0], allr[k])
+    for k in (2, 17, 30):
+        d, c = O.scan_image(ds[k + 1], 0.1, 8.0)
+        pix = np.sort(rng.choice(cam2.width * cam2.height, 1500, replace=False)).astype(np.int64)
+        rend = O.render(mesh, cam2, poses[k], pix)
+        terms = O.icp_terms(rend, mesh, vn, d, c, cam2, poses[k], TOL)
+        keep = ~_icp_flags(rend, terms, cam2)
+        ref = O.icp_reduce(terms, keep)
+        mask = np.zeros(cam2.width * cam2.height, np.uint8)
+        mask[pix[keep]] = 1
+        scans[k].mask = torch.from_numpy(mask.reshape(cam2.height, cam2.width)).to(DEV)
+        g = rm.icp_cost_grad(dm, scans, T, vnd, TOL, poses_per_scan=[1] * 32).cpu().numpy()[k]
+        scans[k].mask = None
+        _compare_icp(g, ref, terms, keep)
+        assert keep.mean() > 0.95 and ref["n_assoc"] > 500
