@@ -166,7 +166,8 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
 // workgroup in jobs of kBand rows: a job brackets the covered span of each of
 // its rows between the three edge crossings (FP64, exact to far below a
 // pixel) and gives only pixel centres inside it the exact int64 edge test.
-constexpr int kQCap = kWG + 32;            // queued sub-triangles per round (more go in-thread)
+constexpr int kQCap = 192;                 // queued sub-triangles per round (more go in-thread); with the
+                                           // 16 KB z-buffer, 40 KB of LDS: four workgroups per CU
 constexpr int kBand = 2;                   // rows per job
 constexpr int kSmallArea = 64;             // bounding-box pixels rasterized by the owning thread
 
@@ -996,7 +997,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
 // first) from a global counter until it runs past the end; every workgroup
 // reaches that exit.
 template <int TW, int TH, int MODE>
-__global__ void __launch_bounds__(kWG, 3) k_raster(BatchDesc bd, RasterArgs a) {
+__global__ void __launch_bounds__(kWG, 4) k_raster(BatchDesc bd, RasterArgs a) {
     __shared__ uint64_t keys[TW * TH];
     __shared__ Queues q;
     __shared__ float red[kWG / 64][kRecFields];
