@@ -519,9 +519,14 @@ __device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
 constexpr float kBigFootprint = 100.0f;    // margin-widened bounding box area, px
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a) {
-    __shared__ uint32_t tcnt[kMaxTiles];       // small count | large count << 16, then cursors
-    __shared__ uint32_t tbs[kMaxTiles], tbb[kMaxTiles];
+__global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t table_n) {
+    // per tile of a cluster's rectangle: small count | large count << 16 (then
+    // cursors), and the two reservations; table_n = the largest tile grid of
+    // the launch, so that the LDS size follows the images of the call
+    extern __shared__ uint32_t tables[];
+    uint32_t* tcnt = tables;
+    uint32_t* tbs = tables + table_n;
+    uint32_t* tbb = tables + 2 * table_n;
     const int pose = blockIdx.y;
     const int nvis = a.vis_count[pose];
     const ScanDesc& sd = bd.s[pose_scan(bd, pose)];
@@ -1253,7 +1258,9 @@ __global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd,
 template <int TW, int TH>
 hipError_t launch_bin_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
     const dim3 grid((unsigned)std::min(a.n_clusters > 0 ? a.n_clusters : 1, 256), (unsigned)bd.n_poses);
-    hipLaunchKernelGGL((k_bin<TW, TH>), grid, dim3(kWG), 0, st, bd, a);
+    int32_t n = 1;
+    for (int s = 0; s < bd.n_scans; ++s) n = std::max(n, bd.s[s].tiles_x * bd.s[s].tiles_y);
+    hipLaunchKernelGGL((k_bin<TW, TH>), grid, dim3(kWG), 3 * sizeof(uint32_t) * (size_t)n, st, bd, a, n);
     return hipGetLastError();
 }
 
