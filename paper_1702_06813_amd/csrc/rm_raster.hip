@@ -82,13 +82,16 @@ constexpr uint64_t kEmptyKey = ~0ull;
 // Depth plane of a triangle in the camera frame, as w = 1/z affine in the
 // pixel offsets: w = a (u - cx) + b (v - cy) + e, with a = n_x/(c fx),
 // b = n_y/(c fy), e = n_z/c for the camera-frame plane n . X = c.  Built in
-// FP64 from the triangle's world unit normal and first vertex, so that long
-// thin triangles keep their depth to ~1e-7 relative.
+// FP64 from the cross product of the triangle's world edges (any length of n
+// gives the same plane) and its first vertex, so that long thin triangles
+// keep their depth to ~1e-7 relative.
 struct WPlane { double a, b, e; };
 
-__device__ __forceinline__ WPlane depth_plane(const PoseF& P, float nw0, float nw1, float nw2, float x0, float y0,
-                                              float z0, double ifx, double ify) {
-    const double n0 = nw0, n1 = nw1, n2 = nw2;
+__device__ __forceinline__ WPlane depth_plane(const PoseF& P, const float v[9], double ifx, double ify) {
+    const float x0 = v[0], y0 = v[1], z0 = v[2];
+    const double e1x = (double)v[3] - x0, e1y = (double)v[4] - y0, e1z = (double)v[5] - z0;
+    const double e2x = (double)v[6] - x0, e2y = (double)v[7] - y0, e2z = (double)v[8] - z0;
+    const double n0 = e1y * e2z - e1z * e2y, n1 = e1z * e2x - e1x * e2z, n2 = e1x * e2y - e1y * e2x;
     const double c = n0 * ((double)x0 - P.t[0]) + n1 * ((double)y0 - P.t[1]) + n2 * ((double)z0 - P.t[2]);
     const double ic = 1.0 / c;
     // camera-frame normal with the f32-rounded rotation (a 6e-8 rotation of the
@@ -323,12 +326,11 @@ __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
 }
 
 // A mesh triangle's inputs, gathered ahead of use: the rounds of a tile
-// pipeline these loads (bin entry, then vertex indices, then vertices and
-// normal) so that the dependent global gathers overlap earlier rounds' work.
+// pipeline these loads (bin entry, then vertex indices, then vertices) so
+// that the dependent global gathers overlap earlier rounds' work.
 struct TriIn {
     int32_t t;             // triangle id, -1 for none
     float v[9];            // world vertices
-    float n[3];            // world unit normal
 };
 
 __device__ __forceinline__ void load_indices(const int32_t* __restrict__ tri, uint32_t vmax, int32_t t,
@@ -338,8 +340,8 @@ __device__ __forceinline__ void load_indices(const int32_t* __restrict__ tri, ui
     for (int k = 0; k < 3; ++k) I[k] = min((uint32_t)tri[3 * (int64_t)t + k], vmax);
 }
 
-__device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, const float* __restrict__ nrm, int32_t t,
-                                              const uint32_t I[3], TriIn& o) {
+__device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, int32_t t, const uint32_t I[3],
+                                              TriIn& o) {
     o.t = t;
     if (t < 0) return;
 #pragma unroll
@@ -348,8 +350,6 @@ __device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, con
         o.v[3 * k + 1] = xyz[3 * (int64_t)I[k] + 1];
         o.v[3 * k + 2] = xyz[3 * (int64_t)I[k] + 2];
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) o.n[k] = nrm[3 * (int64_t)t + k];
 }
 
 // Whole contract for one mesh triangle: transform, far cull, near clip into
@@ -365,7 +365,7 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
     const bool in0 = V0.z >= cam.zn, in1 = V1.z >= cam.zn, in2 = V2.z >= cam.zn;
     const int nin = (int)in0 + (int)in1 + (int)in2;
     if (nin == 0) return;
-    const WPlane pl = depth_plane(P, in.n[0], in.n[1], in.n[2], x0, y0, z0, ifx, ify);
+    const WPlane pl = depth_plane(P, in.v, ifx, ify);
     if (nin == 3) {
         // 1/z over the triangle peaks at its nearest vertex; one pixel of plane
         // extrapolation covers the snapping.  Behind the tile's farthest key at
@@ -789,7 +789,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     uint32_t I1[3], I2[3];
     int32_t t1 = entry(0), t2, t3;
     load_indices(a.tri, a.vmax, t1, I1);
-    load_vertices(a.xyz, a.nrm, t1, I1, cur);
+    load_vertices(a.xyz, t1, I1, cur);
     t1 = entry(1);
     load_indices(a.tri, a.vmax, t1, I1);
     t2 = entry(2);
@@ -798,7 +798,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         if (tid == 0) { q.big.n = 0; q.big.njobs = 0; }
         if (tid <= kSnapTile) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
         const float* rmin = q.rowmin[r & 1];
-        load_vertices(a.xyz, a.nrm, t1, I1, nxt);
+        load_vertices(a.xyz, t1, I1, nxt);
         load_indices(a.tri, a.vmax, t2, I2);
         t3 = entry(r + 3);
         __syncthreads();
