@@ -308,6 +308,17 @@ int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, i
                        const int32_t* pose_off, const double* T_wc, rm_cost_params params,
                        double* out);
 
+/* Table I with reweighted cells (Sec. IV-C suggests adjusting the weights of
+ * the penalties and rewards of the classifications): for each of P result
+ * records of rm_align_cost / rm_align_cost_grad,
+ *   cost_out[p] = sum_k weights[k] * COUNTS_k(p),
+ * over the nine cells in the order of RM_OUT_COUNTS.  The weights
+ * (-1, +1, -1, +1, -1, +1, 0, 0, 0) give E_TABLE.
+ *   out       device [P][RM_OUT_STRIDE] f64
+ *   weights   host, 9 doubles (finite)
+ *   cost_out  device [P] f64 */
+int rm_table_cost_weighted(rm_ctx* ctx, const double* out, int32_t n_poses, const double* weights, double* cost_out);
+
 /* ---------------------------------------------------------------- render-accelerated ICP (Sec. V) */
 
 /* Step 1 of the sequential depth-image alignment (Sec. V-B): keeps every

@@ -556,3 +556,17 @@ def icp_tol_ties(terms, tol):
     with np.errstate(invalid="ignore"):
         scale = DEPTH_REL * np.fmax(np.abs(terms["zM"]), np.abs(terms["z1"]))
         return terms["model"] & (np.abs(np.abs(terms["dz"]) - tol) <= scale)
+
+
+# --------------------------------------------------------------------------
+# Reweighted Table I (Sec. IV-C suggests adjusting the weights of the
+# penalties and rewards per classification)
+# --------------------------------------------------------------------------
+
+TABLE_WEIGHTS = np.array([-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0])   # the values printed in Table I
+
+
+def table_cost_weighted(terms, weights, mask=None):
+    """sum over pixels of the weight of the pixel's Table I cell."""
+    m = np.ones(terms["cell"].shape, bool) if mask is None else np.asarray(mask, bool)
+    return float(np.asarray(weights, np.float64)[terms["cell"][m]].sum())

@@ -8,5 +8,5 @@ from .rendermap import (  # noqa: F401
     OUT_N_VISIBLE, OUT_STRIDE, UO, AlignCost, Context, Graph, Mesh, RenderMapError, Scan, align_cost,
     adam_step, align_cost_grad, context, gn_step, load_library, mesh_from_range, render_depth, scan_image, se3_retract,
     OUT_ICP_COST, OUT_ICP_N_MODEL, OUT_ICP_N_SCAN, OUT_ICP_SSE, depth_downsample, depth_normals, downsample_camera,
-    icp_cost_grad, vertex_normals,
+    icp_cost_grad, vertex_normals, TABLE_WEIGHTS, table_cost_weighted,
 )

@@ -230,9 +230,11 @@ def hybrid_minimize(f, n=6, budget=700, **kw):
     return _drive(_hybrid(n, budget, **kw), f)
 
 
-def plain_align(mesh, scan, T0, eps=0.1, budget=700):
+def plain_align(mesh, scan, T0, eps=0.1, budget=700, weights=None):
     """The paper's plain form: minimize E(X) (Table I) of one pose with the
     derivative-free hybrid optimizer, one single-pose render per evaluation.
+    weights: optional nine Table I cell weights (rm_table_cost_weighted;
+    Sec. IV-C suggests reweighting the penalties and rewards), None for E(X).
     T0: [12] or [3,4] (host).  Returns (T [3,4] numpy, E, evaluations)."""
     dev = mesh.xyz.device
     T0d = torch.as_tensor(np.asarray(T0, np.float64).reshape(1, 12), device=dev)
@@ -244,6 +246,8 @@ def plain_align(mesh, scan, T0, eps=0.1, budget=700):
         xd.copy_(torch.from_numpy(np.asarray(x, np.float64).reshape(1, 6)))
         R.se3_retract(T0d, xd, out=Td)
         R.align_cost(mesh, scan, Td, eps, out=out)
+        if weights is not None:
+            return float(R.table_cost_weighted(out, weights)[0].item())
         return float(out[0, R.OUT_E_TABLE].item())
 
     x, fx, evals = hybrid_minimize(f, budget=budget)
@@ -272,7 +276,7 @@ def lockstep(gens, evaluate):
                 result[k] = stop.value
 
 
-def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None):
+def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weights=None):
     """The paper's optimizer for many alignments at once: every instance runs
     the same hybrid optimizer as plain_align, and each round evaluates the
     next point of every unfinished instance in one launch (T0: [K,3,4] or
@@ -296,7 +300,7 @@ def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None):
         X = torch.from_numpy(np.stack([xs[j] for j in order])).to(dev)
         Td = R.se3_retract(T0d[kk].contiguous(), X)
         out = R.align_cost(mesh, [scans[sc] for sc in used], Td, eps, poses_per_scan=counts)
-        v = out[:, R.OUT_E_TABLE].cpu().numpy()
+        v = (out[:, R.OUT_E_TABLE] if weights is None else R.table_cost_weighted(out, weights)).cpu().numpy()
         res = np.empty(len(ks))
         res[order] = v
         return res

@@ -738,6 +738,19 @@ int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda, d
     return RM_OK;
 }
 
+int rm_table_cost_weighted(rm_ctx* ctx, const double* out, int32_t n_poses, const double* weights, double* cost_out) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (n_poses < 0) return fail(ctx, RM_ERR_INVALID_ARG, "n_poses < 0");
+    if (n_poses == 0) return RM_OK;
+    if (!out || !weights || !cost_out) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(weights[k])) return fail(ctx, RM_ERR_INVALID_ARG, "weights must be finite");
+    DeviceGuard g(ctx->device);
+    RM_HIP(ctx, launch_weighted(ctx->stream, out, n_poses, weights, cost_out));
+    return RM_OK;
+}
+
 int rm_adam_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lr, double beta1, double beta2, int32_t step,
                  double* m, double* v, double* T_wc) {
     if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");

@@ -125,6 +125,8 @@ hipError_t launch_adam_step(hipStream_t st, const double* out, int32_t P, double
                             int32_t step, double* m, double* v, double* T);
 hipError_t launch_retract(hipStream_t st, const double* T_in, const double* delta, int32_t P,
                           double* T_out);
+// cost[p] = sum_k w[k] counts_k of record p (w: host, 9 doubles)
+hipError_t launch_weighted(hipStream_t st, const double* out, int32_t P, const double* w, double* cost);
 
 int64_t meshify_blocks(int32_t H, int32_t W, int32_t stride);
 

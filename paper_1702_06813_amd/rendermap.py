@@ -31,8 +31,9 @@ ABI_SYMBOLS = [
     "rm_get_tile", "rm_set_schedule", "rm_profile", "rm_profile_read", "rm_graph_begin", "rm_graph_end", "rm_graph_launch", "rm_graph_destroy", "rm_scan_image",
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
     "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract", "rm_depth_downsample",
-    "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad",
+    "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad", "rm_table_cost_weighted",
 ]
+TABLE_WEIGHTS = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)   # Table I as printed: reproduces E_TABLE
 
 
 class RenderMapError(RuntimeError):
@@ -103,6 +104,7 @@ def load_library(path: Path | str | None = None):
             "rm_depth_normals": [V, V, I32, I32, F, F, F, I32, V],
             "rm_vertex_normals": [V, V, I32, I32, I32, V, V],
             "rm_icp_cost_grad": [V, ctypes.POINTER(CMesh), V, ctypes.POINTER(CScan), I32, V, V, F, V],
+            "rm_table_cost_weighted": [V, V, I32, V, V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -558,3 +560,15 @@ def icp_cost_grad(mesh, scans, T_wc, vertex_normals: torch.Tensor, tol: float = 
     context(dev).call("rm_icp_cost_grad", ctypes.byref(m), _ptr(vertex_normals), arr, len(scans),
                       ctypes.cast(offs, ctypes.c_void_p), _ptr(T), float(tol), _ptr(out))
     return out
+
+
+def table_cost_weighted(out: torch.Tensor, weights=TABLE_WEIGHTS) -> torch.Tensor:
+    """rm_table_cost_weighted: [P] f64 cost sum_k w_k counts_k of result records."""
+    import numpy as np
+    dev = out.device
+    _need(out, torch.float64, "out", dev)
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(9))
+    P = out.reshape(-1, OUT_STRIDE).shape[0]
+    cost = torch.empty(P, dtype=torch.float64, device=dev)
+    context(dev).call("rm_table_cost_weighted", _ptr(out), P, w.ctypes.data_as(ctypes.c_void_p), _ptr(cost))
+    return cost

@@ -557,3 +557,28 @@ def test_batched_plain_form_matches_plain_form(rm):
         np.testing.assert_array_equal(Tk, T[k])
         assert ek == E[k] and evk == ev[k]
     assert launches == ev.max()
+
+
+def test_table_cost_weighted_matches_oracle(rm):
+    """Reweighted Table I (rm_table_cost_weighted) on the GPU records of the
+    tiny room, over the pixels the oracle does not flag: Table I's printed
+    weights give E_TABLE exactly, and arbitrary weights match the oracle's
+    per-pixel weighted sum."""
+    _say("weighted table cost")
+    w = workload("tiny")
+    mesh = oracle_map("tiny")
+    rng = np.random.default_rng(9)
+    poses = [w.T_true, w.poses[0], S.perturb(w.T_true, rng, 0.05, np.deg2rad(3))]
+    outs = _cost_case(rm, "tiny", poses, None, grad=False)
+    rec = torch.from_numpy(np.stack(outs)).to(DEV)
+    e = rm.table_cost_weighted(rec).cpu().numpy()
+    np.testing.assert_array_equal(e, np.stack(outs)[:, 0])
+    d, c = O.scan_image(w.scan_depth, w.z_min, w.z_max)
+    wt = rng.normal(size=9)
+    g = rm.table_cost_weighted(rec, wt).cpu().numpy()
+    for b, T in enumerate(poses):
+        rend = O.render(mesh, w.cam, T)
+        terms = O.pixel_terms(rend, mesh[2], d, c, w.cam, EPS)
+        keep = ~flagged_pixels(rend, terms, w.cam, EPS)
+        ref = O.table_cost_weighted(terms, wt, keep)
+        assert abs(g[b] - ref) <= 1e-12 * max(1.0, np.abs(wt).sum() * keep.sum()), (g[b], ref)

@@ -484,3 +484,19 @@ def test_contract_snap_exact_arithmetic(oracle_mod):
             assert got == set(pts)
             checked += 1
     assert checked > 20
+
+
+def test_table_weights_as_printed_give_e_table(oracle_mod):
+    """Table I's printed values as cell weights reproduce E(X) exactly, and a
+    weight vector is linear in the cell counts."""
+    O = oracle_mod
+    w = configs.tiny()
+    mesh = w.map_mesh
+    d, c = O.scan_image(w.scan_depth, w.z_min, w.z_max)
+    out = O.align_cost(mesh, w.cam, w.poses[0], d, c, eps=0.1)
+    t = out["terms"]
+    assert O.table_cost_weighted(t, O.TABLE_WEIGHTS) == out["e_table"]
+    rng = np.random.default_rng(8)
+    wt = rng.normal(size=9)
+    np.testing.assert_allclose(O.table_cost_weighted(t, wt), out["counts"] @ wt, rtol=1e-12)
+    assert (np.sign(O.TABLE_WEIGHTS[:6]) == np.array([-1, 1, -1, 1, -1, 1])).all()
