@@ -33,10 +33,13 @@ HBM_PEAK_GBS = 8000.0
 # DRAM bytes of one rasterizer launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # scaled by a plain-copy calibration (profiles/k_raster_differentiation.md);
 # valid only for the rasterizer source and tile they were taken with.
-PROFILED_TRAFFIC = {"rm_raster_sha256_16": "0d1a0a86389c73ea", "tile": [64, 32], "bytes_per_launch": 1348.0e6}
+PROFILED_TRAFFIC = {"rm_raster_sha256_16": "0d1a0a86389c73ea", "tile": [64, 32], "bytes_per_launch": 1348.0e6,
+                    "valu_issue_frac": 0.68}
 
 
-def profiled_traffic(tile):
+def profiled_traffic(tile, field="bytes_per_launch"):
+    """A figure of the committed rocprofv3 summary of the rasterizer, or None
+    once the source or the tile differs from the profiled one."""
     import hashlib
     src = os.path.join(ROOT, "paper_1702_06813_amd", "csrc", "rm_raster.hip")
     try:
@@ -44,7 +47,7 @@ def profiled_traffic(tile):
     except OSError:
         return None
     ok = h == PROFILED_TRAFFIC["rm_raster_sha256_16"] and list(tile) == PROFILED_TRAFFIC["tile"]
-    return PROFILED_TRAFFIC["bytes_per_launch"] if ok else None
+    return PROFILED_TRAFFIC[field] if ok else None
 
 
 def log(msg):
@@ -299,6 +302,7 @@ def main():
                    "tile": tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(tile),
+                     "valu_issue_frac_profiled": profiled_traffic(tile, "valu_issue_frac"),
                      "kernel": "k_raster (grad)", "avg_launch_ms": avg_s * 1e3,
                      "bytes_per_launch": bytes_launch, "visible_tris_per_pose": float(t_vis.mean())},
         "graph_ms_per_step": graph_ms,
