@@ -247,3 +247,39 @@ def test_icp_full_batch_sampled(rm):
         scans[k].mask = None
         _compare_icp(g, ref, terms, keep)
         assert keep.mean() > 0.95 and ref["n_assoc"] > 500
+
+
+def test_icp_empty_and_degenerate(rm):
+    """Degenerate inputs of the ICP path: an all-invalid scan associates
+    nothing; a pose looking away from the model sees no model pixels and its
+    LM step leaves the pose unchanged (H = 0 is not positive definite); the
+    normals of tiny and all-invalid images are all NaN, as in the oracle;
+    zero poses is a no-op."""
+    _say("icp degenerate")
+    cam, mesh, vn, scan_depth, poses = _icp_setup(64, 48)
+    dm = rm.Mesh.from_arrays(*mesh, device=DEV).prepare()
+    vnd = torch.from_numpy(vn).to(DEV)
+    dead = rm.scan_image(torch.full((48, 64), float("nan"), device=DEV), 0.1, 8.0, cam=cam)
+    g = rm.icp_cost_grad(dm, dead, _T(poses[:1]), vnd, TOL).cpu().numpy()[0]
+    assert g[2] == 0 and g[3] == 0 and g[11] == 0 and not g[:2].any() and not g[12:45].any()
+    away = poses[0].copy()
+    away[:, :3] = away[:, :3] @ np.diag([-1.0, 1.0, -1.0])      # turned half round about its y axis
+    scan = rm.scan_image(torch.from_numpy(scan_depth).to(DEV), 0.1, 8.0, cam=cam)
+    T = _T([away])
+    out = rm.icp_cost_grad(dm, scan, T, vnd, TOL)
+    o = out.cpu().numpy()[0]
+    rend = O.render(mesh, cam, away)
+    d, c = O.scan_image(scan_depth, 0.1, 8.0)
+    ref = O.icp_reduce(O.icp_terms(rend, mesh, vn, d, c, cam, away, TOL))
+    assert o[2] == ref["n_scan"] and o[3] == ref["n_model"] == 0 and o[11] == 0
+    T0 = T.clone()
+    rm.gn_step(out, T, 1e-6)
+    assert torch.equal(T, T0)
+    for img in (np.full((2, 3), 2.0, np.float32), np.full((9, 11), np.nan, np.float32)):
+        cam_i = S.Camera(50.0, 50.0, (img.shape[1] - 1) / 2, (img.shape[0] - 1) / 2, img.shape[1], img.shape[0],
+                         0.1, 16.0)
+        n = rm.depth_normals(torch.from_numpy(img).to(DEV), cam_i).cpu().numpy()
+        assert np.isnan(n).all() and np.isnan(O.depth_normals(img, cam_i)).all()
+    empty = rm.icp_cost_grad(dm, scan, torch.zeros((0, 12), dtype=torch.float64, device=DEV), vnd, TOL,
+                             poses_per_scan=[0])
+    assert tuple(empty.shape) == (0, rm.OUT_STRIDE)
