@@ -407,10 +407,16 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
 // Conservative screen footprint of a triangle for binning: approximate
 // float32 camera transform, clip against a plane slightly in front of z_near,
 // projection with the hardware reciprocal; the exact contract is applied
-// later, per tile, so this only has to contain it (2 px margin).
+// later, per tile, so this only has to contain it, widened by the margin m.
 struct Foot {
     float u[4], v[4];      // convex polygon; a triangle repeats its last vertex
+    float m;               // margin, px
 };
+
+// Base margin: covers the 1/512 px vertex snap, the hardware reciprocal and
+// the float32 projection; the float32 camera-centre rounding is added per
+// triangle.
+constexpr float kBinMargin = 0.5f;
 
 __device__ __forceinline__ void proj_approx(const CamF& cam, float3 X, float& u, float& v) {
     const float r = __builtin_amdgcn_rcpf(X.z);
@@ -427,9 +433,11 @@ __device__ __forceinline__ bool footprint(const PoseF& P, const CamF& cam, float
                                           Foot& f) {
     float3 V[3];
     const float3 Wv[3] = {W0, W1, W2};
+    float dm = 0.0f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float d0 = Wv[k].x - P.tf[0], d1 = Wv[k].y - P.tf[1], d2 = Wv[k].z - P.tf[2];
+        dm = fmaxf(dm, fabsf(d0) + fabsf(d1) + fabsf(d2));
         V[k].x = fmaf(P.R[0][2], d2, fmaf(P.R[0][1], d1, P.R[0][0] * d0));
         V[k].y = fmaf(P.R[1][2], d2, fmaf(P.R[1][1], d1, P.R[1][0] * d0));
         V[k].z = fmaf(P.R[2][2], d2, fmaf(P.R[2][1], d1, P.R[2][0] * d0));
@@ -457,6 +465,15 @@ __device__ __forceinline__ bool footprint(const PoseF& P, const CamF& cam, float
         const float3 b = sel3(k == 0 ? 2 : k - 1, V[0], V[1], V[2]);
         Q0 = I; Q1 = clip_approx(I, a, znp); Q2 = clip_approx(I, b, znp); Q3 = Q2;
     }
+    // The contract subtracts the camera centre in FP64 before rounding; here
+    // it is rounded first.  Per camera coordinate the two points differ by
+    // less than 2^-24 (|t| + 9 |d|) (both roundings of the difference, both
+    // float32 rotations), which moves the projection of a point of depth z
+    // at most (f + |u - c|) / z times as far; bounded here with twice that,
+    // the polygon's least depth, and |u - c| up to the larger image side.
+    const float zmin = fmaxf(fminf(Q0.z, fminf(Q1.z, fminf(Q2.z, Q3.z))), znp);
+    const float tn = fabsf(P.tf[0]) + fabsf(P.tf[1]) + fabsf(P.tf[2]);
+    f.m = kBinMargin + 0x1p-23f * (tn + 9.0f * dm) * (fmaxf(cam.fx, cam.fy) + (float)max(cam.W, cam.H)) / zmin;
     proj_approx(cam, Q0, f.u[0], f.v[0]);
     proj_approx(cam, Q1, f.u[1], f.v[1]);
     proj_approx(cam, Q2, f.u[2], f.v[2]);
@@ -465,7 +482,7 @@ __device__ __forceinline__ bool footprint(const PoseF& P, const CamF& cam, float
 }
 
 // Edge functions of the footprint polygon for the tile test: tile (tx, ty),
-// its pixel centres widened by 2 px, certainly misses the polygon when for
+// its pixel centres widened by the margin, certainly misses the polygon when for
 // some edge A x + B y + K < 0 at x = tx * TW, y = ty * TH (A, B the inward
 // normal, K the offset to the rectangle corner farthest inside plus a
 // tolerance above the float rounding of the evaluation).  Degenerate edges
@@ -482,7 +499,7 @@ __device__ __forceinline__ FootEdges foot_edges(const Foot& f, float area2, floa
     for (int i = 0; i < 4; ++i) {
         const int j = (i + 1) & 3;
         const float A = -sg * (f.v[j] - f.v[i]), B = sg * (f.u[j] - f.u[i]);
-        const float ox = A > 0.0f ? (float)(TW + 1) : -2.0f, oy = B > 0.0f ? (float)(TH + 1) : -2.0f;
+        const float ox = A > 0.0f ? (float)(TW - 1) + f.m : -f.m, oy = B > 0.0f ? (float)(TH - 1) + f.m : -f.m;
         const float tol = 1e-4f * (fabsf(A) + fabsf(B)) * (fabsf(f.u[i]) + fabsf(f.v[i]) + W + H + 8.0f) + 1e-6f;
         g.A[i] = A;
         g.B[i] = B;
@@ -516,7 +533,7 @@ __device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
 // rectangle, then reserved with one global atomic per (workgroup, tile,
 // class).  Small footprints fill a bin from the front, large ones from the
 // back, so that the tile pass sees triangles of similar cost together.
-constexpr float kBigFootprint = 100.0f;    // margin-widened bounding box area, px
+constexpr float kBigFootprint = 100.0f;    // bounding box area widened by 2 px per side, px
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t table_n) {
@@ -564,8 +581,8 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
                     vmin = fminf(vmin, f.v[i]); vmax = fmaxf(vmax, f.v[i]);
                     area2 += f.u[i] * f.v[j] - f.u[j] * f.v[i];
                 }
-                umin -= 2.0f; vmin -= 2.0f; umax += 2.0f; vmax += 2.0f;
-                big = (umax - umin) * (vmax - vmin) > kBigFootprint;
+                big = (umax - umin + 4.0f) * (vmax - vmin + 4.0f) > kBigFootprint;
+                umin -= f.m; vmin -= f.m; umax += f.m; vmax += f.m;
                 const float W1f = (float)(cam.W - 1), H1f = (float)(cam.H - 1);
                 ok = umax >= 0.0f && vmax >= 0.0f && umin <= W1f && vmin <= H1f;
                 if (ok) {

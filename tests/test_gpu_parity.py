@@ -158,6 +158,32 @@ def test_render_ragged_image_and_big_triangles(rm):
             rm.context().set_tile(0, 0)
 
 
+def test_render_far_from_origin(rm):
+    """A room 3e5 m from the world origin, where rounding the camera centre
+    to float32 moves the binning footprint by a few pixels: the per-triangle
+    binning margin has to cover it, so that no pixel of the contract is lost
+    at a tile border (the whole frame is compared, at two tile shapes)."""
+    _say("render far from origin")
+    scene = S.random_box_room(7, (4.0, 4.0, 2.5), 8)
+    xyz, tri, cls = S.triangulate_scene(scene, cell=0.1, box_cells=4)
+    off = np.array([3e5, -2.1e5, 0.9e5])
+    mesh = ((xyz.astype(np.float64) + off).astype(np.float32), tri, cls)
+    cam = S.Camera(262.5, 262.5, 79.5, 59.5, 160, 120, z_near=0.1, z_far=16.0)
+    rng = np.random.default_rng(6)
+    poses = []
+    for _ in range(4):
+        T = np.array(S.look_pose(np.array([rng.uniform(1, 3), rng.uniform(1, 3), rng.uniform(0.8, 1.8)]),
+                                 rng.uniform(0, 6.28), rng.uniform(-0.5, 0.5), rng.uniform(-0.3, 0.3)), np.float64)
+        T[:3, 3] += off
+        poses.append(T)
+    for tile in ((16, 16), (64, 32)):
+        rm.context().set_tile(*tile)
+        try:
+            _render_cmp(rm, mesh, cam, poses)
+        finally:
+            rm.context().set_tile(0, 0)
+
+
 def test_render_kinect_sampled(rm):
     _say("render kinect")
     w = workload("kinect")
