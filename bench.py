@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # DRAM bytes of one rasterizer launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # scaled by a plain-copy calibration (profiles/k_raster_differentiation.md);
 # valid only for the rasterizer source and tile they were taken with.
-PROFILED_TRAFFIC = {"rm_raster_sha256_16": "2a776c8c73fde3d4", "tile": [64, 32], "bytes_per_launch": 1238.1e6,
+PROFILED_TRAFFIC = {"rm_raster_sha256_16": "8494694705af0ef6", "tile": [64, 32], "bytes_per_launch": 1221.4e6,
                     "valu_issue_frac": 0.68}
 
 

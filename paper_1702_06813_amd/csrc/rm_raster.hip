@@ -416,7 +416,7 @@ struct Foot {
 // Base margin: covers the 1/512 px vertex snap, the hardware reciprocal and
 // the float32 projection; the float32 camera-centre rounding is added per
 // triangle.
-constexpr float kBinMargin = 0.5f;
+constexpr float kBinMargin = 0.25f;
 
 __device__ __forceinline__ void proj_approx(const CamF& cam, float3 X, float& u, float& v) {
     const float r = __builtin_amdgcn_rcpf(X.z);
