@@ -51,7 +51,7 @@ typedef enum {
     RM_ERR_OOM = -2,           /* device scratch could not be allocated */
     RM_ERR_DEVICE = -3,        /* a HIP runtime call failed */
     RM_ERR_CAPACITY = -4,      /* output capacity too small, or scratch must grow during graph capture */
-    RM_ERR_UNSUPPORTED = -5    /* valid request this build does not support */
+    RM_ERR_UNSUPPORTED = -5    /* valid request the library does not support */
 } rm_status;
 
 /* Interface classes of Sec. IV-A (free-occupied, free-unknown,
