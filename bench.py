@@ -34,7 +34,13 @@ HBM_PEAK_GBS = 8000.0
 # scaled by a plain-copy calibration (profiles/k_raster_differentiation.md);
 # valid only for the rasterizer source and tile they were taken with.
 PROFILED_TRAFFIC = {"rm_raster_sha256_16": "8494694705af0ef6", "tile": [64, 32], "bytes_per_launch": 1221.4e6,
-                    "valu_issue_frac": 0.68}
+                    "valu_issue_frac": 0.68,
+                    # SQ_INSTS_LDS_ATOMIC_BANDWIDTH x 8: 64-bit LDS atomic lanes of one
+                    # rasterizer launch (an upper bound: the few 32-bit queue counters
+                    # count as well), and TCC_ATOMIC_sum of one binning launch and its
+                    # profiled duration (profiles/atomics_differentiation.md)
+                    "lds_atomic_lanes_per_launch": 4.103e8, "bin_global_atomics_per_launch": 7.455e5,
+                    "bin_launch_ms": 1.072}
 
 
 def profiled_traffic(tile, field="bytes_per_launch"):
@@ -48,6 +54,38 @@ def profiled_traffic(tile, field="bytes_per_launch"):
         return None
     ok = h == PROFILED_TRAFFIC["rm_raster_sha256_16"] and list(tile) == PROFILED_TRAFFIC["tile"]
     return PROFILED_TRAFFIC[field] if ok else None
+
+
+def atomic_peaks(sweep=False):
+    """Throughput peaks of the LDS 64-bit minimum (the depth-key resolve, per
+    lane) and of the global 32-bit add with return (bin reservations), from
+    librm_microbench.so; None where that library was not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1702_06813_amd", "librm_microbench.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.rm_mb_lds_min_u64.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.rm_mb_global_atomic_add.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.rm_mb_lds_min_u64.restype = lib.rm_mb_global_atomic_add.restype = ctypes.c_int
+    sec, ops = ctypes.c_double(), ctypes.c_double()
+
+    def rate(rc):
+        return ops.value / sec.value if rc == 0 and sec.value > 0 else None
+
+    lds, glob = {}, {}
+    for blocks in ((1024, 2048, 4096) if sweep else (2048,)):
+        lds[blocks] = rate(lib.rm_mb_lds_min_u64(blocks, 8192, ctypes.byref(sec), ctypes.byref(ops)))
+    for slots_log2 in ((12, 15, 20) if sweep else (15,)):
+        glob[slots_log2] = rate(lib.rm_mb_global_atomic_add(2048, 256, slots_log2, ctypes.byref(sec),
+                                                            ctypes.byref(ops)))
+    best = lambda d: max((v for v in d.values() if v), default=None)
+    out = {"lds_min_u64_lane_ops_per_s": best(lds), "global_atomic_add_per_s": best(glob)}
+    if sweep:
+        out["lds_by_blocks"] = lds
+        out["global_by_slots_log2"] = glob
+    return out
 
 
 def log(msg):
@@ -205,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alignment", action="store_true", help="skip the batched-vs-plain alignment comparison")
     ap.add_argument("--no-icp", action="store_true", help="skip the render-accelerated ICP odometry (Sec. V)")
+    ap.add_argument("--atomic-peaks", action="store_true",
+                    help="only run the atomic-throughput microbenchmarks (a small sweep of launch shapes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -217,6 +257,10 @@ def main():
     import paper_1702_06813_amd as rm
 
     dev = torch.device("cuda:0")
+    if args.atomic_peaks:
+        torch.zeros(1, device=dev)
+        print(json.dumps(atomic_peaks(sweep=True)), flush=True)
+        return
     if args.copy_calibration:
         n = args.copy_calibration << 20
         src = torch.ones(n // 4, dtype=torch.float32, device=dev)
@@ -306,7 +350,19 @@ def main():
                      "kernel": "k_raster (grad)", "avg_launch_ms": avg_s * 1e3,
                      "bytes_per_launch": bytes_launch, "visible_tris_per_pose": float(t_vis.mean())},
         "graph_ms_per_step": graph_ms,
+        "atomics": atomic_peaks(),
     }
+    if res["atomics"]:
+        a = res["atomics"]
+        lanes = profiled_traffic(tile, "lds_atomic_lanes_per_launch")
+        if lanes is not None and a["lds_min_u64_lane_ops_per_s"]:
+            a["k_raster_lds_atomic_lane_ops_per_s"] = lanes / avg_s
+            a["k_raster_lds_atomic_frac"] = lanes / avg_s / a["lds_min_u64_lane_ops_per_s"]
+        n_glob = profiled_traffic(tile, "bin_global_atomics_per_launch")
+        if n_glob is not None and a["global_atomic_add_per_s"]:
+            rate = n_glob / (profiled_traffic(tile, "bin_launch_ms") * 1e-3)
+            a["k_bin_global_atomics_per_s_profiled"] = rate
+            a["k_bin_global_atomic_frac"] = rate / a["global_atomic_add_per_s"]
     if not args.no_alignment:
         res["alignment"] = alignment_comparison(rm, torch, w, mesh, scan, T0)
     if not args.no_icp:

@@ -85,3 +85,22 @@ def test_binding_fails_loudly_without_gpu():
     import paper_1702_06813_amd as rm
     with pytest.raises(RuntimeError):
         rm.Context(0)
+
+
+def test_microbenchmark_library_exports_and_rejects_bad_arguments():
+    """The atomic-throughput microbenchmarks the benchmark reports beside the
+    roofline: both symbols exported, out-of-range arguments rejected (-1)
+    before any device call."""
+    path = ROOT / "paper_1702_06813_amd" / "librm_microbench.so"
+    if not path.exists():
+        pytest.skip("microbenchmark library not built")
+    mb = ctypes.CDLL(str(path))
+    dp = ctypes.POINTER(ctypes.c_double)
+    mb.rm_mb_lds_min_u64.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+    mb.rm_mb_global_atomic_add.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+    s, n = ctypes.c_double(), ctypes.c_double()
+    assert mb.rm_mb_lds_min_u64(0, 8, ctypes.byref(s), ctypes.byref(n)) == -1
+    assert mb.rm_mb_lds_min_u64(16, 0, ctypes.byref(s), ctypes.byref(n)) == -1
+    assert mb.rm_mb_global_atomic_add(16, 8, 5, ctypes.byref(s), ctypes.byref(n)) == -1
+    assert mb.rm_mb_global_atomic_add(16, 8, 25, ctypes.byref(s), ctypes.byref(n)) == -1
+    assert mb.rm_mb_global_atomic_add(16, 8, 12, None, ctypes.byref(n)) == -1
