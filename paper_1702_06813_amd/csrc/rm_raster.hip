@@ -86,23 +86,30 @@ constexpr uint64_t kEmptyKey = ~0ull;
 // gives the same plane) and its first vertex, so that long thin triangles
 // keep their depth to ~1e-7 relative.
 struct WPlane { double a, b, e; };
+struct PlaneN { double nx, ny, nz, c; };   // camera-frame normal and offset n . X = c
 
-__device__ __forceinline__ WPlane depth_plane(const PoseF& P, const float v[9], double ifx, double ify) {
+__device__ __forceinline__ PlaneN plane_normal(const PoseF& P, const float v[9]) {
     const float x0 = v[0], y0 = v[1], z0 = v[2];
     const double e1x = (double)v[3] - x0, e1y = (double)v[4] - y0, e1z = (double)v[5] - z0;
     const double e2x = (double)v[6] - x0, e2y = (double)v[7] - y0, e2z = (double)v[8] - z0;
     const double n0 = e1y * e2z - e1z * e2y, n1 = e1z * e2x - e1x * e2z, n2 = e1x * e2y - e1y * e2x;
-    const double c = n0 * ((double)x0 - P.t[0]) + n1 * ((double)y0 - P.t[1]) + n2 * ((double)z0 - P.t[2]);
-    const double ic = 1.0 / c;
+    PlaneN q;
+    q.c = n0 * ((double)x0 - P.t[0]) + n1 * ((double)y0 - P.t[1]) + n2 * ((double)z0 - P.t[2]);
     // camera-frame normal with the f32-rounded rotation (a 6e-8 rotation of the
     // plane about its anchor vertex, far below the depth tolerance)
-    const double nx = (double)P.R[0][0] * n0 + (double)P.R[0][1] * n1 + (double)P.R[0][2] * n2;
-    const double ny = (double)P.R[1][0] * n0 + (double)P.R[1][1] * n1 + (double)P.R[1][2] * n2;
-    const double nz = (double)P.R[2][0] * n0 + (double)P.R[2][1] * n1 + (double)P.R[2][2] * n2;
+    q.nx = (double)P.R[0][0] * n0 + (double)P.R[0][1] * n1 + (double)P.R[0][2] * n2;
+    q.ny = (double)P.R[1][0] * n0 + (double)P.R[1][1] * n1 + (double)P.R[1][2] * n2;
+    q.nz = (double)P.R[2][0] * n0 + (double)P.R[2][1] * n1 + (double)P.R[2][2] * n2;
+    return q;
+}
+
+// 1/z over the image: w(u, v) = a (u - cx) + b (v - cy) + e.
+__device__ __forceinline__ WPlane depth_plane(const PlaneN& q, double ifx, double ify) {
+    const double ic = 1.0 / q.c;
     WPlane p;
-    p.a = nx * ic * ifx;
-    p.b = ny * ic * ify;
-    p.e = nz * ic;
+    p.a = q.nx * ic * ifx;
+    p.b = q.ny * ic * ify;
+    p.e = q.nz * ic;
     return p;
 }
 
@@ -354,6 +361,7 @@ __device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, int
 
 // Whole contract for one mesh triangle: transform, far cull, near clip into
 // at most two sub-triangles (same id), setup and rasterization.
+template <int MODE>
 __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queues& q, const float* rmin,
                                                 const Tile& tl, const CamF& cam, double ifx, double ify, float w_far,
                                                 const PoseF& P, const TriIn& in) {
@@ -365,13 +373,29 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
     const bool in0 = V0.z >= cam.zn, in1 = V1.z >= cam.zn, in2 = V2.z >= cam.zn;
     const int nin = (int)in0 + (int)in1 + (int)in2;
     if (nin == 0) return;
-    const WPlane pl = depth_plane(P, in.v, ifx, ify);
-    if (nin == 3) {
-        // 1/z over the triangle peaks at its nearest vertex; one pixel of plane
-        // extrapolation covers the snapping.  Behind the tile's farthest key at
-        // the round start, no pixel of the triangle can change.
-        const double wv = 1.0 / (double)fminf(V0.z, fminf(V1.z, V2.z)) + fabs(pl.a) + fabs(pl.b);
-        if (wv * 1.00001 < (double)rmin[kSnapTile]) return;
+    const PlaneN pn = plane_normal(P, in.v);
+    // 1/z over the triangle peaks at its nearest vertex; one pixel of plane
+    // extrapolation covers the snapping.  Behind the tile's farthest key at
+    // the round start, no pixel of the triangle can change:
+    // (1/z_min + |a| + |b|) (1 + 1e-5) < w_key.  Outside ICP mode the test is
+    // taken multiplied by z_min |c| > 0, so that a skipped triangle needs no
+    // division (c = 0, a plane through the camera centre, is never skipped);
+    // in ICP mode the plane first (fewer registers live across the test there).
+    WPlane pl;
+    if constexpr (MODE == kIcp) {
+        pl = depth_plane(pn, ifx, ify);
+        if (nin == 3) {
+            const double wv = 1.0 / (double)fminf(V0.z, fminf(V1.z, V2.z)) + fabs(pl.a) + fabs(pl.b);
+            if (wv * 1.00001 < (double)rmin[kSnapTile]) return;
+        }
+    } else {
+        if (nin == 3) {
+            const double zmin = (double)fminf(V0.z, fminf(V1.z, V2.z));
+            const double ac = fabs(pn.c);
+            const double lhs = (ac + zmin * (fabs(pn.nx) * ifx + fabs(pn.ny) * ify)) * 1.00001;
+            if (lhs < (double)rmin[kSnapTile] * zmin * ac) return;
+        }
+        pl = depth_plane(pn, ifx, ify);
     }
     const uint32_t id = (uint32_t)in.t;
     // near-plane clip into at most two sub-triangles; one emit call site keeps
@@ -819,7 +843,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         load_indices(a.tri, a.vmax, t2, I2);
         t3 = entry(r + 3);
         __syncthreads();
-        if (cur.t >= 0) raster_triangle(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
+        if (cur.t >= 0) raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
         __syncthreads();
         if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
         __syncthreads();
