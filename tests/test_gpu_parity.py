@@ -184,6 +184,43 @@ def test_render_far_from_origin(rm):
             rm.context().set_tile(0, 0)
 
 
+def test_duplicate_triangles_lowest_id_wins(rm):
+    """Every triangle of the tiny room twice, the two copies at shuffled
+    positions (ids): at every pixel the GPU's triangle id is the lower id of
+    the two copies of the triangle the oracle sees there.  The copies tie
+    exactly, so this is checked directly, without the near-tie exemption;
+    only pixels where two different triangles of the original mesh nearly
+    tie are left out."""
+    _say("render duplicate triangles")
+    w = workload("tiny")
+    xyz, tri, cls = w.map_mesh
+    n = len(tri)
+    rng = np.random.default_rng(17)
+    pos = rng.permutation(2 * n)                 # copy a of t at pos[2t], copy b at pos[2t+1]
+    tri2 = np.empty((2 * n, 3), np.int32)
+    cls2 = np.empty(2 * n, np.uint8)
+    tri2[pos[0::2]] = tri; tri2[pos[1::2]] = tri
+    cls2[pos[0::2]] = cls; cls2[pos[1::2]] = cls
+    low = np.minimum(pos[0::2], pos[1::2])
+    dm = _dev_mesh(rm, (xyz, tri2, cls2))
+    poses = [w.T_true, w.poses[0]] + [S.perturb(w.T_true, rng, 0.3, np.deg2rad(30)) for _ in range(4)]
+    out = rm.render_depth(dm, w.cam, _T(poses))
+    gt = out["tri"].cpu().numpy()
+    for b, T in enumerate(poses):
+        rend = O.render(w.map_mesh, w.cam, T)
+        fl = O.flags(rend, w.cam)
+        ok = ~(fl["near_tie"] | fl["far_tie"])
+        exp = np.where(rend["id"] >= 0, low[np.maximum(rend["id"], 0)], -1)
+        got = gt[b].reshape(-1)
+        assert ok.mean() > 0.97
+        np.testing.assert_array_equal(got[ok], exp[ok])
+        # the oracle on the duplicated mesh agrees: lower copy, exact tie
+        rend2 = O.render((xyz, tri2, cls2), w.cam, T)
+        np.testing.assert_array_equal(rend2["id"][ok], exp[ok])
+        hit = ok & (rend2["id"] >= 0)
+        np.testing.assert_array_equal(rend2["z2"][hit], rend2["z"][hit])
+
+
 def test_render_kinect_sampled(rm):
     _say("render kinect")
     w = workload("kinect")
