@@ -64,7 +64,9 @@ typedef struct rm_ctx rm_ctx;
  * Surfaces nearer than z_near are clipped, farther than z_far ignored. */
 typedef struct {
     float fx, fy, cx, cy;
-    int32_t width, height;     /* 1 .. 4096 each */
+    int32_t width, height;     /* 1 .. 4096 each (a tile shape with more than
+                                  256 tiles per image row or column is
+                                  RM_ERR_UNSUPPORTED: 8x8 tiles above 2048) */
     float z_near, z_far;       /* 0 < z_near < z_far */
 } rm_camera;
 
@@ -176,9 +178,19 @@ int rm_ctx_set_stream(rm_ctx* ctx, void* stream);
  * message of the last failed rm_ctx_create or NULL-context call. */
 const char* rm_last_error(const rm_ctx* ctx);
 /* Selects the screen-tile shape of the rasterizer: tile_w x tile_h one of
- * 16x16, 32x32, 64x32; (0, 0) restores automatic choice (autotuned when
- * rm_autotune is on, 64x32 otherwise).  Results do not depend on it. */
+ * 8x8, 16x16, 32x32, 64x32; (0, 0) restores automatic choice (autotuned when
+ * rm_autotune is on, 64x32 otherwise).  Results do not depend on it.  A
+ * scoring call whose images need more than 256 tiles of the chosen shape per
+ * row or column, or 2^31 or more (pose, tile) pairs, returns
+ * RM_ERR_UNSUPPORTED. */
 int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
+/* Capacity of the per-(pose, screen tile) triangle bins, in entries.  0 (the
+ * default) adapts it: the first call of a launch shape sizes the bins from
+ * the binning pass and later calls grow them from earlier calls' largest
+ * fill.  cap > 0 fixes it and never grows it; a bin that overflows is then
+ * rasterized from every visible cluster of its pose instead (slower, same
+ * result).  cap in 0 .. 2^24, else RM_ERR_INVALID_ARG. */
+int rm_set_bin_cap(rm_ctx* ctx, int32_t cap);
 /* Work scheduling of the rasterizer over (scan, pose, tile) items:
  *   0  automatic: currently 2, measured faster for single- and multi-scan
  *      batches alike
@@ -191,12 +203,15 @@ int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
  * Returns RM_ERR_INVALID_ARG for other values. */
 int rm_set_schedule(rm_ctx* ctx, int32_t mode);
 /* Turns the tile autotuner on or off.  When on, the first call for a new
- * (image size, pose count, triangle count) times the tile shapes on the
- * call's own inputs, largest first, stopping at the first shape more than
- * 25% slower than the best so far, and keeps the fastest for later calls of
- * that shape. */
+ * launch shape (every scan's image size and pose count, the triangle count
+ * and the kind of call) times the tile shapes 64x32, 32x32, 16x16 and 8x8 on
+ * the call's own inputs, largest first, skipping shapes the batch cannot use
+ * (see rm_set_tile) and stopping at the first shape more than 25% slower than
+ * the best so far, and keeps the fastest for later calls of that shape.  With
+ * the environment variable RM_LOG set, each choice is printed to stderr. */
 int rm_autotune(rm_ctx* ctx, int32_t enable);
-/* Current tile choice for a shape (after autotuning), for reporting. */
+/* Current tile choice for a single-scan shape (after autotuning), for
+ * reporting: the explicit tile, else the tuned one, else 64x32. */
 int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int64_t n_tris,
                 int32_t* tile_w, int32_t* tile_h);
 

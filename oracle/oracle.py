@@ -366,6 +366,20 @@ def gn_step(out, lam=0.0):
     return -np.linalg.solve(A, out["jtr"])
 
 
+def adam_step(grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps_adam=1e-12):
+    """One Adam update of a pose increment from the se(3) gradient (Kingma
+    and Ba's first and second moment estimates with bias correction):
+        m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+        delta = -lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps_adam).
+    Returns (delta, m, v) as new arrays; the pose then moves by T exp(delta)."""
+    g = np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return -lr * mhat / (np.sqrt(vhat) + eps_adam), m, v
+
+
 def fd_jacobian(mesh, cam, T_wc, pixels, scan_d, scan_c, h=1e-4, mode="contract"):
     """Central finite differences of the unclamped E_soft residual e_p =
     dz |n^ . ray| with respect to the six components of delta.  Returns

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -28,13 +29,18 @@ struct rm_ctx {
     int tile_w = 0, tile_h = 0;       // 0 = automatic
     int schedule = 0;                 // 0 automatic (= 2), 1 one workgroup per item, 2 persistent longest-first
     bool autotune = false;
-    std::map<std::tuple<int, int, int, int64_t, int>, std::pair<int, int>> tuned;
+    // tuned tile per launch shape: {mode, n_tris, n_scans, then width, height,
+    // pose count of every scan}
+    std::map<std::vector<int64_t>, std::pair<int, int>> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
     size_t prof_used = 0;
-    // tile-bin capacity, adapted from the largest bin of earlier calls
+    // tile-bin capacity, adapted from the largest bin of earlier calls, unless
+    // fixed by rm_set_bin_cap (then never grown: overflowing bins take the
+    // every-cluster path)
     int32_t bin_cap = 1024;
+    int32_t bin_cap_fixed = 0;
     hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bin
     bool bin_pending = false;
     // launch shapes whose bins were sized by a synchronous check after binning
@@ -143,13 +149,14 @@ int check_mesh(rm_ctx* ctx, const rm_mesh* m) {
 }
 
 bool valid_tile(int w, int h) {
-    return (w == 16 && h == 16) || (w == 32 && h == 32) || (w == 64 && h == 32);
+    return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 32) || (w == 64 && h == 32);
 }
 
 // Autotune candidates, largest first: each step down quadruples or doubles
 // the per-pose tile records and bins, so the search stops at the first shape
 // that is clearly slower than the best so far.
-const int kTiles[3][2] = {{64, 32}, {32, 32}, {16, 16}};
+constexpr int kNumTiles = 4;
+const int kTiles[kNumTiles][2] = {{64, 32}, {32, 32}, {16, 16}, {8, 8}};
 
 // Fills the scan descriptors and counts items and partial records.
 void plan(BatchDesc& bd, int tw, int th) {
@@ -175,7 +182,30 @@ int64_t total_records(const BatchDesc& bd) {
     return r;
 }
 
+// Whether a batch can run with tile tw x th: at most kMaxTileGrid tiles per
+// image row and column (tile rectangles are packed in 8-bit fields) and fewer
+// than 2^31 (pose, tile) records in the call.  Empty on success, otherwise
+// the reason.
+std::string tile_limit(const BatchDesc& bd0, int tw, int th) {
+    BatchDesc bd = bd0;
+    plan(bd, tw, th);
+    char buf[160];
+    for (int s = 0; s < bd.n_scans; ++s)
+        if (bd.s[s].tiles_x > kMaxTileGrid || bd.s[s].tiles_y > kMaxTileGrid) {
+            snprintf(buf, sizeof(buf), "%dx%d image needs more than %d tiles of %dx%d per row or column",
+                     bd.s[s].width, bd.s[s].height, kMaxTileGrid, tw, th);
+            return buf;
+        }
+    if (total_records(bd) >= ((int64_t)1 << 31)) {
+        snprintf(buf, sizeof(buf), "%lld (pose, tile) records of %dx%d tiles exceed 2^31 - 1",
+                 (long long)total_records(bd), tw, th);
+        return buf;
+    }
+    return std::string();
+}
+
 constexpr int64_t kMaxBinBytes = (int64_t)32 << 30;   // largest tile-bin allocation
+constexpr int64_t kMinBinCap = 64;                     // the budget never shrinks a bin below this
 
 // Grows the bin capacity when the largest bin of an earlier call (read back
 // asynchronously) did not fit; never while capturing.
@@ -193,31 +223,35 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
 // One scoring pass: cull, near-to-far cluster order, bin, rasterize (+ fused
 // comparison), reduce.
 int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
-             float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out, const float* vnrm = nullptr) {
+             float eps, double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out, const float* vnrm,
+             const Arena& arena) {
+    {
+        const std::string why = tile_limit(bd, tw, th);
+        if (!why.empty()) return fail(ctx, RM_ERR_UNSUPPORTED, "%s", why.c_str());
+    }
     plan(bd, tw, th);
-    for (int s = 0; s < bd.n_scans; ++s)
-        if (bd.s[s].tiles_x * bd.s[s].tiles_y > kMaxTiles || bd.s[s].tiles_x > 256 || bd.s[s].tiles_y > 256)
-            return fail(ctx, RM_ERR_UNSUPPORTED, "%dx%d image needs more than %d tiles of %dx%d", bd.s[s].width,
-                        bd.s[s].height, kMaxTiles, tw, th);
     const int P = bd.n_poses;
     const int64_t C = (mesh->n_tris + kClusterTris - 1) / kClusterTris;
     const int64_t R = total_records(bd);
+    const bool fixed_cap = ctx->bin_cap_fixed > 0;
     adapt_bin_cap(ctx, R);
     // The first uncaptured call of a launch shape reads the largest bin fill
     // back right after binning and, if the bins were too small, grows them and
     // bins again, so that no call of that shape takes the slow every-cluster
-    // path of an overflowing bin; later calls adapt asynchronously.
+    // path of an overflowing bin; later calls adapt asynchronously.  A fixed
+    // capacity (rm_set_bin_cap) or a fixed scratch buffer is never grown.
     const auto shape = std::make_tuple(R, tw, th, mesh->n_tris, P);
-    const bool check = !capturing(ctx) && ctx->bin_checked.count(shape) == 0;
+    const bool check = !fixed_cap && !arena.fixed && !capturing(ctx) && ctx->bin_checked.count(shape) == 0;
     const bool persistent = ctx->schedule != 1;
     RasterArgs a;
     int32_t* vis_count = nullptr;
     int32_t* vis_tris = nullptr;
     int32_t* bin_max = nullptr;
     for (int attempt = 0;; ++attempt) {
-        // the capacity learned so far, limited to what this call's records may take
-        int64_t cap = ctx->bin_cap;
-        while (cap > 1024 && R * cap * 4 > kMaxBinBytes) cap /= 2;
+        // the capacity learned so far (or fixed), limited to what this call's records may take
+        int64_t cap = fixed_cap ? ctx->bin_cap_fixed : ctx->bin_cap;
+        if (!fixed_cap)
+            while (cap > kMinBinCap && R * cap * 4 > kMaxBinBytes) cap /= 2;
         Carve cv;
         // vis_count, vis_tris, bin_max, bin_fill[2], bin fills, order histogram and cursors, queue
         const int64_t n_cnt = 2 * (int64_t)P + 3 + 2 * R + 65;
@@ -227,10 +261,25 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         const size_t o_visz = cv.take<float>((int64_t)P * C);
         const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
         const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
-        const size_t o_bin = cv.take<uint32_t>(R * cap);
-        int rc = ensure_scratch(ctx, cv.off);
-        if (rc) return rc;
-        vis_count = at<int32_t>(ctx, o_cnt);
+        const size_t o_bin = cv.off;
+        char* base = nullptr;
+        if (arena.fixed) {
+            // bins take what the fixed buffer leaves; a bin that overflows a
+            // smaller capacity is rasterized from every visible cluster (same result)
+            if (o_bin + 256 > arena.fixed_size)
+                return fail(ctx, RM_ERR_CAPACITY, "the call needs %zu bytes of scratch besides its bins; the "
+                                                  "allocation-free buffer holds %zu", o_bin + 256, arena.fixed_size);
+            cap = std::min<int64_t>(cap, (int64_t)((arena.fixed_size - o_bin) / 4) / std::max<int64_t>(R, 1));
+            cv.take<uint32_t>(R * cap);
+            base = arena.fixed;
+        } else {
+            cv.take<uint32_t>(R * cap);
+            int rc = ensure_scratch(ctx, cv.off);
+            if (rc) return rc;
+            base = static_cast<char*>(ctx->scratch);
+        }
+        auto at = [&](size_t off) { return base + off; };
+        vis_count = reinterpret_cast<int32_t*>(at(o_cnt));
         vis_tris = vis_count + P;
         bin_max = vis_tris + P;
         int32_t* bin_fill = bin_max + 1;
@@ -239,7 +288,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         int32_t* hist = bin_big + R;
         const void* prep = mesh->clusters;
         if (!prep && C > 0) {
-            void* w = at<char>(ctx, o_cb);
+            void* w = at(o_cb);
             RM_HIP(ctx, launch_prepare(ctx->stream, mesh->xyz, mesh->n_vertices, mesh->tri, mesh->n_tris, w));
             prep = w;
         }
@@ -248,8 +297,8 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
                                                                  prepared_normals_offset(mesh->n_tris))
                                 : nullptr;
         RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, n_cnt));
-        uint2* vis = at<uint2>(ctx, o_vis);
-        float* vis_z = at<float>(ctx, o_visz);
+        uint2* vis = reinterpret_cast<uint2*>(at(o_vis));
+        float* vis_z = reinterpret_cast<float*>(at(o_visz));
         RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_z, vis_count, vis_tris));
         RM_HIP(ctx, launch_vis_sort(ctx->stream, bd, (int32_t)C, vis_count, vis_z, vis));
         a.xyz = mesh->xyz;
@@ -262,7 +311,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.T_wc = T_wc;
         a.vis = vis;
         a.vis_count = vis_count;
-        a.bins = at<uint32_t>(ctx, o_bin);
+        a.bins = reinterpret_cast<uint32_t*>(at(o_bin));
         a.bin_small = bin_small;
         a.bin_big = bin_big;
         a.bin_max = bin_max;
@@ -271,7 +320,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.order = nullptr;
         a.queue = hist + 64;
         a.n_order = (int32_t)R;
-        a.rec = at<float>(ctx, o_rec);
+        a.rec = reinterpret_cast<float*>(at(o_rec));
         a.eps = eps;
         a.vnrm = vnrm;
         a.depth_out = depth_out;
@@ -279,7 +328,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.cls_out = cls_out;
         RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
         if (persistent) {
-            int32_t* order = at<int32_t>(ctx, o_ord);
+            int32_t* order = reinterpret_cast<int32_t*>(at(o_ord));
             RM_HIP(ctx, launch_order(ctx->stream, bd, bin_small, bin_big, R, hist, order));
             a.order = order;
         }
@@ -292,12 +341,12 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         if (need <= cap) break;
         int64_t grown = cap;
         while (grown < need + need / 4 && grown < ((int64_t)1 << 24)) grown *= 2;
-        while (grown > 1024 && R * grown * 4 > kMaxBinBytes) grown /= 2;
+        while (grown > kMinBinCap && R * grown * 4 > kMaxBinBytes) grown /= 2;
         if (grown <= cap) break;               // cannot grow: overflowing bins take the slow path
         ctx->bin_cap = (int32_t)std::max<int64_t>(grown, ctx->bin_cap);
     }
     hipEvent_t pe1 = nullptr;
-    if (ctx->profiling && !capturing(ctx)) {
+    if (ctx->profiling && !capturing(ctx) && !arena.fixed) {
         if (ctx->prof_used == ctx->prof_events.size()) {
             hipEvent_t x, y;
             RM_HIP(ctx, hipEventCreate(&x));
@@ -312,7 +361,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     if (pe1) RM_HIP(ctx, hipEventRecord(pe1, ctx->stream));
     if (mode != kRender)
         RM_HIP(ctx, launch_reduce(ctx->stream, bd, a.rec, vis_tris, eps, mode, out));
-    if (!capturing(ctx) && !ctx->bin_pending) {
+    if (!capturing(ctx) && !ctx->bin_pending && !arena.fixed) {
         if (!ctx->bin_ev) RM_HIP(ctx, hipEventCreateWithFlags(&ctx->bin_ev, hipEventDisableTiming));
         RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, bin_max, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
         RM_HIP(ctx, hipEventRecord(ctx->bin_ev, ctx->stream));
@@ -321,25 +370,41 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     return RM_OK;
 }
 
+// Tuning key of a launch shape: mode, triangle count, and every scan's image
+// size and pose count.
+std::vector<int64_t> tune_key(const BatchDesc& bd, int64_t n_tris, int mode) {
+    std::vector<int64_t> k = {mode, n_tris, bd.n_scans};
+    for (int s = 0; s < bd.n_scans; ++s) {
+        k.push_back(bd.s[s].width);
+        k.push_back(bd.s[s].height);
+        k.push_back(bd.s[s].n_poses);
+    }
+    return k;
+}
+
 // Chooses the tile shape (explicit, cached autotune result, or default) and runs.
 int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const double* T_wc, float eps,
-               double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out, const float* vnrm = nullptr) {
+               double* out, float* depth_out, int32_t* tri_out, uint8_t* cls_out, const float* vnrm,
+               const Arena& arena) {
     if (ctx->tile_w) return run_pass(ctx, mesh, bd, ctx->tile_w, ctx->tile_h, mode, T_wc, eps, out, depth_out,
-                                     tri_out, cls_out, vnrm);
-    const auto key = std::make_tuple(bd.s[0].width, bd.s[0].height, bd.n_poses, mesh->n_tris, mode);
+                                     tri_out, cls_out, vnrm, arena);
+    if (arena.fixed)
+        return run_pass(ctx, mesh, bd, 64, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out, vnrm, arena);
+    const std::vector<int64_t> key = tune_key(bd, mesh->n_tris, mode);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end())
         return run_pass(ctx, mesh, bd, it->second.first, it->second.second, mode, T_wc, eps, out, depth_out,
-                        tri_out, cls_out, vnrm);
+                        tri_out, cls_out, vnrm, arena);
     if (!ctx->autotune || capturing(ctx))
-        return run_pass(ctx, mesh, bd, 64, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out, vnrm);
+        return run_pass(ctx, mesh, bd, 64, 32, mode, T_wc, eps, out, depth_out, tri_out, cls_out, vnrm, arena);
     if (!ctx->ev0) {
         RM_HIP(ctx, hipEventCreate(&ctx->ev0));
         RM_HIP(ctx, hipEventCreate(&ctx->ev1));
     }
     float best = 1e30f;
-    int bi = 0;
-    for (int k = 0; k < 3; ++k) {
+    int bi = -1;
+    for (int k = 0; k < kNumTiles; ++k) {
+        if (!tile_limit(bd, kTiles[k][0], kTiles[k][1]).empty()) continue;   // not possible for this batch
         // one warm-up and one timed pass per shape; the warm-up's largest bin
         // is read back first so that the timed pass runs with bins that fit
         for (int rep = 0; rep < 2; ++rep) {
@@ -348,7 +413,7 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
                 RM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
             }
             int rc = run_pass(ctx, mesh, bd, kTiles[k][0], kTiles[k][1], mode, T_wc, eps, out, depth_out, tri_out,
-                              cls_out, vnrm);
+                              cls_out, vnrm, arena);
             if (rc) return rc;
         }
         RM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -358,8 +423,16 @@ int run_scored(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int mode, const 
         if (ms < best) { best = ms; bi = k; }
         else if (ms > 1.25f * best) break;
     }
+    if (bi < 0) {
+        const std::string why = tile_limit(bd, kTiles[kNumTiles - 1][0], kTiles[kNumTiles - 1][1]);
+        return fail(ctx, RM_ERR_UNSUPPORTED, "no tile shape fits this batch: %s", why.c_str());
+    }
     ctx->tuned[key] = {kTiles[bi][0], kTiles[bi][1]};
-    return run_pass(ctx, mesh, bd, kTiles[bi][0], kTiles[bi][1], mode, T_wc, eps, out, depth_out, tri_out, cls_out, vnrm);
+    if (getenv("RM_LOG"))
+        fprintf(stderr, "[rendermap] autotune: %d scans, %d poses, %lld triangles: tile %dx%d (%.3f ms)\n",
+                bd.n_scans, bd.n_poses, (long long)mesh->n_tris, kTiles[bi][0], kTiles[bi][1], best);
+    return run_pass(ctx, mesh, bd, kTiles[bi][0], kTiles[bi][1], mode, T_wc, eps, out, depth_out, tri_out, cls_out,
+                    vnrm, arena);
 }
 
 int fill_scan(rm_ctx* ctx, ScanDesc& d, const rm_camera& c) {
@@ -371,8 +444,11 @@ int fill_scan(rm_ctx* ctx, ScanDesc& d, const rm_camera& c) {
     return RM_OK;
 }
 
-int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t S, const int32_t* pose_off,
-                 const double* T_wc, rm_cost_params params, double* out, int mode, const float* vnrm = nullptr) {
+}  // namespace
+
+int rm::align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t S, const int32_t* pose_off,
+                     const double* T_wc, rm_cost_params params, double* out, int mode, const float* vnrm,
+                     const Arena* arena) {
     if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
     ctx->err.clear();
     int rc = check_mesh(ctx, mesh);
@@ -404,8 +480,14 @@ int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t
     if (!T_wc || !out) return fail(ctx, RM_ERR_INVALID_ARG, "T_wc and out must be non-NULL");
     bd.n_poses = P;
     DeviceGuard g(ctx->device);
-    return run_scored(ctx, mesh, bd, mode, T_wc, params.eps, out, nullptr, nullptr, nullptr, vnrm);
+    const Arena none;
+    return run_scored(ctx, mesh, bd, mode, T_wc, params.eps, out, nullptr, nullptr, nullptr, vnrm,
+                      arena ? *arena : none);
 }
+
+int rm::ctx_fail(rm_ctx* ctx, int code, const char* msg) { return fail(ctx, code, "%s", msg); }
+
+namespace {
 
 }  // namespace
 
@@ -482,12 +564,21 @@ int rm_autotune(rm_ctx* ctx, int32_t enable) {
     return RM_OK;
 }
 
+int rm_set_bin_cap(rm_ctx* ctx, int32_t cap) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (cap < 0 || cap > (1 << 24)) return fail(ctx, RM_ERR_INVALID_ARG, "bin capacity %d outside 0..2^24", cap);
+    ctx->bin_cap_fixed = cap;
+    return RM_OK;
+}
+
 int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int64_t n_tris, int32_t* tile_w,
                 int32_t* tile_h) {
     if (!ctx || !tile_w || !tile_h) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
     if (ctx->tile_w) { *tile_w = ctx->tile_w; *tile_h = ctx->tile_h; return RM_OK; }
-    for (int mode = kCost; mode <= kGrad; ++mode) {
-        auto it = ctx->tuned.find(std::make_tuple(width, height, n_poses, n_tris, mode));
+    for (int mode = kCost; mode <= kIcp; ++mode) {
+        const std::vector<int64_t> key = {mode, n_tris, 1, width, height, n_poses};
+        auto it = ctx->tuned.find(key);
         if (it != ctx->tuned.end()) { *tile_w = it->second.first; *tile_h = it->second.second; return RM_OK; }
     }
     *tile_w = 64;
@@ -643,17 +734,18 @@ int rm_render_depth(rm_ctx* ctx, const rm_mesh* mesh, rm_camera cam, const doubl
     bd.s[0].n_poses = n_poses;
     DeviceGuard g(ctx->device);
     const int tw = ctx->tile_w ? ctx->tile_w : 64, th = ctx->tile_w ? ctx->tile_h : 32;
-    return run_pass(ctx, mesh, bd, tw, th, kRender, T_wc, 1.0f, nullptr, depth_out, tri_out, cls_out);
+    return run_pass(ctx, mesh, bd, tw, th, kRender, T_wc, 1.0f, nullptr, depth_out, tri_out, cls_out, nullptr,
+                    Arena());
 }
 
 int rm_align_cost(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans, const int32_t* pose_off,
                   const double* T_wc, rm_cost_params params, double* out) {
-    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kCost);
+    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kCost, nullptr, nullptr);
 }
 
 int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
                        const int32_t* pose_off, const double* T_wc, rm_cost_params params, double* out) {
-    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kGrad);
+    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, params, out, kGrad, nullptr, nullptr);
 }
 
 int rm_depth_downsample(rm_ctx* ctx, const float* depth, int32_t height, int32_t width, int32_t factor, float z_max,
@@ -723,7 +815,7 @@ int rm_icp_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const float* vertex_norma
     rm_cost_params p;
     p.eps = tol;
     p.flags = 0;
-    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, p, out, kIcp, vertex_normals);
+    return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, p, out, kIcp, vertex_normals, nullptr);
 }
 
 int rm_gn_step(rm_ctx* ctx, const double* out, int32_t n_poses, double lambda, double* T_wc, double* delta_out) {

@@ -13,7 +13,9 @@ constexpr int kClusterTris = RM_CLUSTER_TRIS;
 constexpr int kQuadBlock = 8;            // meshify emits 8x8 blocks of quads
 constexpr int kRecFields = 40;           // per-(pose, tile) partial record, 4-byte fields
 constexpr int kSnapLimit = 1 << 29;      // |snapped coordinate| must stay below this
-constexpr int kMaxTiles = 2048;          // screen tiles per image (bin-pass LDS tables)
+constexpr int kBinTable = 2048;          // tiles of a cluster rectangle binned per LDS pass (taller
+                                         // rectangles are binned in bands of rows)
+constexpr int kMaxTileGrid = 256;        // tiles per image row and column (8-bit rectangle fields)
 
 // Per-cluster bounds written by rm_mesh_clusters: world AABB.
 struct ClusterBounds {
@@ -129,5 +131,19 @@ hipError_t launch_retract(hipStream_t st, const double* T_in, const double* delt
 hipError_t launch_weighted(hipStream_t st, const double* out, int32_t P, const double* w, double* cost);
 
 int64_t meshify_blocks(int32_t H, int32_t W, int32_t stride);
+
+// Scratch of one scoring call: the context's own arena, grown on demand
+// (fixed == nullptr), or a fixed device buffer that the call may not grow.
+struct Arena {
+    char* fixed = nullptr;
+    size_t fixed_size = 0;
+};
+// Validation, batch description, tile choice and the scoring pass of
+// rm_align_cost / rm_align_cost_grad / rm_icp_cost_grad (host runtime).
+int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t S, const int32_t* pose_off,
+                 const double* T_wc, rm_cost_params params, double* out, int mode, const float* vnrm,
+                 const Arena* arena);
+// Records an error message on the context and returns code.
+int ctx_fail(rm_ctx* ctx, int code, const char* msg);
 
 }  // namespace rm

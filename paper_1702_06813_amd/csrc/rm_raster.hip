@@ -561,9 +561,12 @@ constexpr float kBigFootprint = 100.0f;    // bounding box area widened by 2 px 
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t table_n) {
-    // per tile of a cluster's rectangle: small count | large count << 16 (then
-    // cursors), and the two reservations; table_n = the largest tile grid of
-    // the launch, so that the LDS size follows the images of the call
+    // per tile of a band of a cluster's rectangle: small count | large count
+    // << 16 (then cursors), and the two reservations.  table_n = the largest
+    // tile grid of the launch, at most kBinTable, so that the LDS size follows
+    // the images of the call; a rectangle with more tiles is binned in bands
+    // of whole tile rows (table_n >= its width: rows hold at most
+    // kMaxTileGrid <= kBinTable tiles).
     extern __shared__ uint32_t tables[];
     uint32_t* tcnt = tables;
     uint32_t* tbs = tables + table_n;
@@ -581,9 +584,10 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
     for (int k = blockIdx.x; k < nvis; k += gridDim.x) {
         const uint2 e = a.vis[(int64_t)pose * a.n_clusters + k];
         const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
-        const int rw = rx1 - rx0 + 1, nrect = rw * (ry1 - ry0 + 1);
+        const int rw = rx1 - rx0 + 1;
+        const int brows = min(ry1 - ry0 + 1, table_n / rw);     // tile rows per band
         __syncthreads();                       // previous item's tables are no longer read
-        for (int i = threadIdx.x; i < nrect; i += kWG) tcnt[i] = 0;
+        for (int i = threadIdx.x; i < brows * rw; i += kWG) tcnt[i] = 0;
         const int64_t t = (int64_t)e.x * kClusterTris + threadIdx.x;
         Foot f;
         bool ok = false, big = false;
@@ -641,74 +645,89 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
             }
         }
         const uint32_t inc = big ? 0x10000u : 1u;
-        __syncthreads();
-        if (masked) {
-            for (uint64_t m = hits; m; m &= m - 1) {      // only the tiles hit
-                const int i = __ffsll((unsigned long long)m) - 1;
-                atomicAdd(&tcnt[(ty0 + (i >> ls) - ry0) * rw + (tx0 + (i & ((1 << ls) - 1)) - rx0)], inc);
-            }
-        } else {
-            for (int r = 0; r < sh; ++r) {
-                float k[4];
-                edges_row(g, (float)((ty0 + r) * TH), k);
-                for (int c = 0; c < sw; ++c)
-                    if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW)))
-                        atomicAdd(&tcnt[(ty0 + r - ry0) * rw + (tx0 + c - rx0)], inc);
-            }
-        }
-        __syncthreads();
-        int fs = 0, fb = 0;                    // largest fills this thread reserved
-        for (int i = threadIdx.x; i < nrect; i += kWG) {
-            const uint32_t n = tcnt[i];
-            if (n) {
-                const int tile = (ry0 + i / rw) * sd.tiles_x + rx0 + i % rw;
-                if (n & 0xffffu) {
-                    tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
-                    fs = max(fs, (int)(tbs[i] + (n & 0xffffu)));
+        for (int by0 = ry0;;) {
+            const int by1 = min(ry1, by0 + brows - 1);
+            const int nb = (by1 - by0 + 1) * rw;
+            // the footprint's tile rows inside this band
+            const int r0 = max(ty0, by0) - ty0, r1 = min(ty1, by1) - ty0;
+            // (bits [r0 << ls, (r1 + 1) << ls) of the mask; r0 << ls < 64 when masked)
+            const uint64_t band_bits =
+                !masked || r0 > r1
+                    ? 0ull
+                    : (((r1 + 1) << ls) >= 64 ? ~0ull : (1ull << ((r1 + 1) << ls)) - 1ull) & ~((1ull << (r0 << ls)) - 1ull);
+            __syncthreads();                   // the band's counters are zero
+            if (masked) {
+                for (uint64_t m = hits & band_bits; m; m &= m - 1) {      // only the tiles hit
+                    const int i = __ffsll((unsigned long long)m) - 1;
+                    atomicAdd(&tcnt[(ty0 + (i >> ls) - by0) * rw + (tx0 + (i & ((1 << ls) - 1)) - rx0)], inc);
                 }
-                if (n >> 16) {
-                    tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
-                    fb = max(fb, (int)(tbb[i] + (n >> 16)));
-                }
-                tcnt[i] = 0;
-            }
-        }
-        if (a.bin_fill) {                      // only when the host sizes the bins of a new shape
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                fs = max(fs, __shfl_xor(fs, off));
-                fb = max(fb, __shfl_xor(fb, off));
-            }
-            if ((threadIdx.x & 63) == 0 && (fs | fb)) {
-                atomicMax(a.bin_fill, fs);
-                atomicMax(a.bin_fill + 1, fb);
-            }
-        }
-        __syncthreads();
-        auto put = [&](int tx, int ty) {
-            const int li = (ty - ry0) * rw + (tx - rx0);
-            const uint32_t old = atomicAdd(&tcnt[li], inc);
-            uint32_t* bin = a.bins + (rec0 + ty * sd.tiles_x + tx) * (int64_t)cap;
-            if (big) {
-                const uint32_t slot = tbb[li] + (old >> 16);
-                if (slot < cap) bin[cap - 1 - slot] = (uint32_t)t;
             } else {
-                const uint32_t slot = tbs[li] + (old & 0xffffu);
-                if (slot < cap) bin[slot] = (uint32_t)t;
+                for (int r = r0; r <= r1; ++r) {
+                    float k[4];
+                    edges_row(g, (float)((ty0 + r) * TH), k);
+                    for (int c = 0; c < sw; ++c)
+                        if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW)))
+                            atomicAdd(&tcnt[(ty0 + r - by0) * rw + (tx0 + c - rx0)], inc);
+                }
             }
-        };
-        if (masked) {
-            for (uint64_t m = hits; m; m &= m - 1) {
-                const int i = __ffsll((unsigned long long)m) - 1;
-                put(tx0 + (i & ((1 << ls) - 1)), ty0 + (i >> ls));
+            __syncthreads();
+            int fs = 0, fb = 0;                    // largest fills this thread reserved
+            for (int i = threadIdx.x; i < nb; i += kWG) {
+                const uint32_t n = tcnt[i];
+                if (n) {
+                    const int tile = (by0 + i / rw) * sd.tiles_x + rx0 + i % rw;
+                    if (n & 0xffffu) {
+                        tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
+                        fs = max(fs, (int)(tbs[i] + (n & 0xffffu)));
+                    }
+                    if (n >> 16) {
+                        tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
+                        fb = max(fb, (int)(tbb[i] + (n >> 16)));
+                    }
+                    tcnt[i] = 0;
+                }
             }
-        } else {
-            for (int r = 0; r < sh; ++r) {
-                float k[4];
-                edges_row(g, (float)((ty0 + r) * TH), k);
-                for (int c = 0; c < sw; ++c)
-                    if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW))) put(tx0 + c, ty0 + r);
+            if (a.bin_fill) {                      // only when the host sizes the bins of a new shape
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    fs = max(fs, __shfl_xor(fs, off));
+                    fb = max(fb, __shfl_xor(fb, off));
+                }
+                if ((threadIdx.x & 63) == 0 && (fs | fb)) {
+                    atomicMax(a.bin_fill, fs);
+                    atomicMax(a.bin_fill + 1, fb);
+                }
             }
+            __syncthreads();
+            auto put = [&](int tx, int ty) {
+                const int li = (ty - by0) * rw + (tx - rx0);
+                const uint32_t old = atomicAdd(&tcnt[li], inc);
+                uint32_t* bin = a.bins + (rec0 + ty * sd.tiles_x + tx) * (int64_t)cap;
+                if (big) {
+                    const uint32_t slot = tbb[li] + (old >> 16);
+                    if (slot < cap) bin[cap - 1 - slot] = (uint32_t)t;
+                } else {
+                    const uint32_t slot = tbs[li] + (old & 0xffffu);
+                    if (slot < cap) bin[slot] = (uint32_t)t;
+                }
+            };
+            if (masked) {
+                for (uint64_t m = hits & band_bits; m; m &= m - 1) {
+                    const int i = __ffsll((unsigned long long)m) - 1;
+                    put(tx0 + (i & ((1 << ls) - 1)), ty0 + (i >> ls));
+                }
+            } else {
+                for (int r = r0; r <= r1; ++r) {
+                    float k[4];
+                    edges_row(g, (float)((ty0 + r) * TH), k);
+                    for (int c = 0; c < sw; ++c)
+                        if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW))) put(tx0 + c, ty0 + r);
+                }
+            }
+            by0 = by1 + 1;
+            if (by0 > ry1) break;
+            __syncthreads();                   // the put cursors of this band are no longer read
+            for (int i = threadIdx.x; i < brows * rw; i += kWG) tcnt[i] = 0;
         }
     }
 }
@@ -1301,6 +1320,8 @@ hipError_t launch_bin_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a
     const dim3 grid((unsigned)std::min(a.n_clusters > 0 ? a.n_clusters : 1, 256), (unsigned)bd.n_poses);
     int32_t n = 1;
     for (int s = 0; s < bd.n_scans; ++s) n = std::max(n, bd.s[s].tiles_x * bd.s[s].tiles_y);
+    n = std::min(n, kBinTable);
+    static_assert(kMaxTileGrid <= kBinTable, "a row of tiles must fit one binning band");
     hipLaunchKernelGGL((k_bin<TW, TH>), grid, dim3(kWG), 3 * sizeof(uint32_t) * (size_t)n, st, bd, a, n);
     return hipGetLastError();
 }
@@ -1398,6 +1419,7 @@ hipError_t launch_vis_sort(hipStream_t st, const BatchDesc& bd, int32_t n_cluste
 
 hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
     if (bd.n_items == 0 || a.n_clusters == 0) return hipSuccess;
+    if (bd.tile_w == 8 && bd.tile_h == 8) return launch_bin_t<8, 8>(st, bd, a);
     if (bd.tile_w == 16 && bd.tile_h == 16) return launch_bin_t<16, 16>(st, bd, a);
     if (bd.tile_w == 64 && bd.tile_h == 32) return launch_bin_t<64, 32>(st, bd, a);
     return launch_bin_t<32, 32>(st, bd, a);
@@ -1439,6 +1461,7 @@ int resident_t(int mode) {
 }  // namespace
 
 int persistent_grid(int tile_w, int tile_h, int mode) {
+    if (tile_w == 8 && tile_h == 8) return resident_t<8, 8>(mode);
     if (tile_w == 16 && tile_h == 16) return resident_t<16, 16>(mode);
     if (tile_w == 64 && tile_h == 32) return resident_t<64, 32>(mode);
     return resident_t<32, 32>(mode);
@@ -1446,6 +1469,7 @@ int persistent_grid(int tile_w, int tile_h, int mode) {
 
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode) {
     if (bd.n_items == 0) return hipSuccess;
+    if (bd.tile_w == 8 && bd.tile_h == 8) return launch_raster_t<8, 8>(st, bd, a, mode);
     if (bd.tile_w == 16 && bd.tile_h == 16) return launch_raster_t<16, 16>(st, bd, a, mode);
     if (bd.tile_w == 64 && bd.tile_h == 32) return launch_raster_t<64, 32>(st, bd, a, mode);
     return launch_raster_t<32, 32>(st, bd, a, mode);

@@ -31,7 +31,7 @@ ABI_SYMBOLS = [
     "rm_get_tile", "rm_set_schedule", "rm_profile", "rm_profile_read", "rm_graph_begin", "rm_graph_end", "rm_graph_launch", "rm_graph_destroy", "rm_scan_image",
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
     "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract", "rm_depth_downsample",
-    "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad", "rm_table_cost_weighted",
+    "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad", "rm_table_cost_weighted", "rm_set_bin_cap",
 ]
 TABLE_WEIGHTS = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)   # Table I as printed: reproduces E_TABLE
 
@@ -83,6 +83,7 @@ def load_library(path: Path | str | None = None):
             "rm_set_tile": [V, I32, I32],
             "rm_autotune": [V, I32],
             "rm_set_schedule": [V, I32],
+            "rm_set_bin_cap": [V, I32],
             "rm_get_tile": [V, I32, I32, I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)],
             "rm_profile": [V, I32],
             "rm_profile_read": [V, ctypes.POINTER(I64), ctypes.POINTER(D)],
@@ -153,6 +154,10 @@ class Context:
     def set_schedule(self, mode: int):
         """rm_set_schedule: 0 automatic (persistent), 1 one workgroup per item, 2 persistent longest-first."""
         self.call("rm_set_schedule", int(mode))
+
+    def set_bin_cap(self, cap: int):
+        """rm_set_bin_cap: fixed tile-bin capacity in entries (0: adaptive)."""
+        _check(self.lib.rm_set_bin_cap(self.handle, int(cap)), self.handle)
 
     def autotune(self, enable: bool = True):
         _check(self.lib.rm_autotune(self.handle, int(enable)), self.handle)
@@ -394,12 +399,34 @@ def align_cost_grad(mesh, scans, T_wc, eps=0.1, poses_per_scan=None, out=None):
     return _align("rm_align_cost_grad", mesh, scans, poses_per_scan, T_wc, eps, out)
 
 
+def _records(out, P, dev):
+    _need(out, torch.float64, "out", dev)
+    if tuple(out.shape) != (P, OUT_STRIDE):
+        raise ValueError(f"out must be [{P}, {OUT_STRIDE}], got {tuple(out.shape)}")
+    return out
+
+
+def _pose_count(T_wc):
+    if T_wc.numel() % 12 or T_wc.shape[-1] not in (4, 12):
+        raise ValueError(f"T_wc must hold [P, 12] (or [P, 3, 4]) poses, got {tuple(T_wc.shape)}")
+    return T_wc.numel() // 12
+
+
+def _per_pose(t, P, n, dtype, name, dev):
+    _need(t, dtype, name, dev)
+    if tuple(t.shape) != (P, n):
+        raise ValueError(f"{name} must be [{P}, {n}], got {tuple(t.shape)}")
+    return t
+
+
 def gn_step(out: torch.Tensor, T_wc: torch.Tensor, lam: float = 0.0, delta_out=None):
     """rm_gn_step: T_wc <- T_wc exp(-(H + lam diag H)^-1 b), in place."""
     dev = T_wc.device
     T = _need(T_wc, torch.float64, "T_wc", dev)
-    _need(out, torch.float64, "out", dev)
-    P = T.reshape(-1, 12).shape[0]
+    P = _pose_count(T)
+    _records(out, P, dev)
+    if delta_out is not None:
+        _per_pose(delta_out, P, 6, torch.float64, "delta_out", dev)
     context(dev).call("rm_gn_step", _ptr(out), P, float(lam), _ptr(T), _ptr(delta_out))
     return T_wc
 
@@ -409,10 +436,10 @@ def adam_step(out: torch.Tensor, T_wc: torch.Tensor, m: torch.Tensor, v: torch.T
     """rm_adam_step: Adam on the se(3) increment from the GRAD field; T_wc, m, v in place."""
     dev = T_wc.device
     T = _need(T_wc, torch.float64, "T_wc", dev)
-    _need(out, torch.float64, "out", dev)
-    _need(m, torch.float64, "m", dev)
-    _need(v, torch.float64, "v", dev)
-    P = T.reshape(-1, 12).shape[0]
+    P = _pose_count(T)
+    _records(out, P, dev)
+    _per_pose(m, P, 6, torch.float64, "m", dev)
+    _per_pose(v, P, 6, torch.float64, "v", dev)
     context(dev).call("rm_adam_step", _ptr(out), P, float(lr), float(beta1), float(beta2), int(step), _ptr(m),
                       _ptr(v), _ptr(T))
     return T_wc
@@ -422,9 +449,13 @@ def se3_retract(T_wc: torch.Tensor, delta: torch.Tensor, out=None):
     """rm_se3_retract: T_wc exp(delta) for every pose."""
     dev = T_wc.device
     T = _poses(T_wc, dev)
-    d = _need(delta.contiguous(), torch.float64, "delta", dev)
+    P = T.shape[0]
+    d = _per_pose(delta.contiguous(), P, 6, torch.float64, "delta", dev)
     o = torch.empty_like(T) if out is None else out
-    context(dev).call("rm_se3_retract", _ptr(T), _ptr(d), T.shape[0], _ptr(o))
+    _need(o, torch.float64, "out", dev)
+    if o.numel() != 12 * P:
+        raise ValueError(f"out must hold {P} poses of 12 doubles, got {tuple(o.shape)}")
+    context(dev).call("rm_se3_retract", _ptr(T), _ptr(d), P, _ptr(o))
     return o
 
 

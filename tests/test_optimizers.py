@@ -62,3 +62,44 @@ def test_lockstep_equals_one_at_a_time():
         np.testing.assert_array_equal(x1, x2)
         assert f1 == f2 and e1 == e2
     assert rounds == max(e for _, _, e in alone)
+
+
+# ---------------------------------------------------------------- Adam (oracle pins)
+
+def test_adam_first_step_is_lr_times_sign(oracle_mod):
+    """With zero moments, bias correction makes the first step
+    -lr g / (|g| + 1e-12) per component: -lr sign(g) up to the guard."""
+    O = oracle_mod
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=6) * 10.0 ** rng.uniform(-3, 3, 6)
+    d, m, v = O.adam_step(g, np.zeros(6), np.zeros(6), 1, lr=0.01)
+    np.testing.assert_allclose(d, -0.01 * g / (np.abs(g) + 1e-12), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_constant_gradient_keeps_unit_steps(oracle_mod):
+    """A constant gradient gives m_hat = g and v_hat = g^2 at every step, so
+    every step is -lr g / (|g| + 1e-12): a wrong bias correction drifts from it."""
+    O = oracle_mod
+    g = np.array([3.0, -0.5, 1e-3, -2e2, 7.0, 0.25])
+    m, v = np.zeros(6), np.zeros(6)
+    for k in range(1, 40):
+        d, m, v = O.adam_step(g, m, v, k, lr=0.05, beta1=0.8, beta2=0.95)
+        np.testing.assert_allclose(d, -0.05 * g / (np.abs(g) + 1e-12), rtol=1e-12)
+
+
+def test_adam_converges_on_quadratic_bowl(oracle_mod):
+    """Adam on f(x) = 1/2 (x - c)^T A (x - c) with an ill-conditioned A reaches
+    the minimum c to within a fraction of the step size."""
+    O = oracle_mod
+    A = np.diag([100.0, 10.0, 1.0, 0.1, 3.0, 30.0])
+    c = np.array([0.3, -0.2, 0.1, 0.05, -0.4, 0.25])
+    x = np.zeros(6)
+    m, v = np.zeros(6), np.zeros(6)
+    lr = 0.01
+    for k in range(1, 3001):
+        lr_k = lr * (0.999 ** k)
+        d, m, v = O.adam_step(A @ (x - c), m, v, k, lr=lr_k)
+        x = x + d
+    assert np.abs(x - c).max() < 1e-3, x - c
