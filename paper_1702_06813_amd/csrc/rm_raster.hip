@@ -126,6 +126,20 @@ constexpr double kOccMargin = 1.0 + 1e-6;
 // (index row * kSegs + x / kSeg) and the tile's farthest at kSnapTile.
 constexpr int kSeg = 16, kSegs = 4, kSnapTile = 32 * kSegs;
 
+// Minimum of x over aligned groups of G consecutive lanes (G = 8 or 16, one
+// DPP row or half row): swaps inside quads, then the half-row and row
+// mirrors; every lane of a group ends with the group's minimum.  All lanes of
+// the wave must be active.
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t x) {
+    static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
+    x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    if constexpr (G == 16) x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false));   // row_mirror
+    return x;
+}
+
 // Farthest snapshot w over the segments that columns [x0, x1] of row y touch.
 __device__ __forceinline__ float snap_min(const float* rmin, int y, int x0, int x1) {
     const float* r = rmin + y * kSegs;
@@ -856,7 +870,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     if (tid <= kSnapTile) q.rowmin[0][tid] = 0.0f;   // round 0 sees an empty buffer
     for (int r = 0; r < nr; ++r) {
         if (tid == 0) { q.big.n = 0; q.big.njobs = 0; }
-        if (tid <= kSnapTile) q.rowmin[(r + 1) & 1][tid] = __int_as_float(0x7f800000);
+        if (tid == 0) q.rowmin[(r + 1) & 1][kSnapTile] = __int_as_float(0x7f800000);
         const float* rmin = q.rowmin[r & 1];
         load_vertices(a.xyz, t1, I1, nxt);
         load_indices(a.tri, a.vmax, t2, I2);
@@ -867,15 +881,25 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
         __syncthreads();
         // row and tile snapshot for the next round (w >= 0, so its bits order
-        // like its value)
+        // like its value).  Pixel p = tid + k kWG lies in row p / TW, so the
+        // kG lanes of a group cover one kSeg-pixel segment (or, for 8-pixel
+        // tile rows, one row): a group minimum and one store per segment;
+        // the tile's farthest is a wave minimum and one atomic per wave.
         if (r + 1 < nr) {
+            constexpr int kG = TW < kSeg ? TW : kSeg;
+            float* snap = q.rowmin[(r + 1) & 1];
             uint32_t tmin = 0x7f800000u;
             for (int p = tid; p < TW * TH; p += kWG) {
-                const uint32_t wb = ~(uint32_t)(keys[p] >> 32);
-                atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][(p / TW) * kSegs + (p % TW) / kSeg], wb);
+                const uint32_t wb = group_min<kG>(~(uint32_t)(keys[p] >> 32));
+                if ((lane & (kG - 1)) == 0) snap[(p / TW) * kSegs + (p % TW) / kSeg] = __uint_as_float(wb);
                 tmin = min(tmin, wb);
             }
-            atomicMin((unsigned int*)&q.rowmin[(r + 1) & 1][kSnapTile], tmin);
+            if (tid < TW * TH) {
+                tmin = min(tmin, (uint32_t)__shfl_xor((int)tmin, 16));
+                tmin = min(tmin, (uint32_t)__shfl_xor((int)tmin, 32));
+                if constexpr (kG == 8) tmin = min(tmin, (uint32_t)__shfl_xor((int)tmin, 8));
+                if (lane == 0) atomicMin((unsigned int*)&snap[kSnapTile], tmin);
+            }
         }
         cur = nxt;
         t1 = t2;

@@ -717,19 +717,25 @@ def test_autograd_function_matches_oracle_gradient(rm):
 
 def test_autograd_gradient_matches_central_differences(rm):
     """Central differences of the GPU's own E_soft through AlignCost, step
-    1e-4 (m / rad) on each se(3) axis, against the gradient AlignCost returns,
+    1e-3 (m / rad) on each se(3) axis, against the gradient AlignCost returns,
     over pixels whose winning triangle, Table I cell and active state are the
-    same at all 13 poses (the oracle decides, and flags none of them).  The
-    tolerance, 2e-4 of the L1 mass of the per-pixel gradient terms, covers the
-    float32 depth key (relative 2^-24 of z, which moves rho by up to
-    4 |r| 2^-24 z / eps^2 per pixel) divided by the 2e-4 of the difference,
-    and the float32 tile sums."""
+    same at all 13 poses (the oracle decides, and flags none of them).
+
+    Step and tolerance follow from the float32 arithmetic of the cost: the
+    depth key holds w = 1/z rounded to float32 and z = 1/w is formed in
+    float32, so each pixel's residual carries an error of order 2^-23 z and
+    its rho one of order 4 |r| 2^-23 z / eps^2 (about 3e-6 at z = 3 m,
+    r = 5 cm); summed over the ~2,800 pixels this is E_soft's ~1e-3 offset
+    from the FP64 oracle, which the difference quotient divides by 2h.  At
+    h = 1e-4 that is ~5e-4 of the gradient's L1 mass (measured), at h = 1e-3
+    ~5e-5, inside the 2e-4 allowed here.  (The oracle's own FP64 finite
+    differences are checked at h = 1e-4 on the CPU.)"""
     _say("autograd central differences")
     w = workload("tiny")
     dm = _dev_mesh(rm, w.map_mesh)
     d, c = O.scan_image(w.scan_depth)
     T = w.poses[0]
-    h = 1e-4
+    h = 1e-3
     ref = O.align_cost(w.map_mesh, w.cam, T, d, c, eps=EPS)
     t0 = ref["terms"]
     keep = ~flagged_pixels(ref["render"], t0, w.cam, EPS)
