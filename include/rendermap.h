@@ -323,6 +323,26 @@ int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, i
                        const int32_t* pose_off, const double* T_wc, rm_cost_params params,
                        double* out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rm_align_cost_grad
+ * with every scratch buffer of the call (visible-cluster lists, bin counters,
+ * tile bins, per-tile partial records, cluster bounds when mesh->clusters is
+ * NULL) carved from a fixed 256 MiB device array that the library holds on
+ * each device it runs on until the process ends.  Arguments, outputs and
+ * results are those of rm_align_cost_grad; the call never allocates, never
+ * synchronizes and never autotunes (it uses the tile set by rm_set_tile, else
+ * 64x32).  When the tile bins do not fit beside the rest, their capacity is
+ * lowered and overflowing tiles are rasterized from every visible cluster of
+ * their pose (slower, same records).  A call whose scratch without bins
+ * exceeds the array (about 12 bytes per (pose, cluster) plus 160 bytes per
+ * (pose, tile), plus 12 bytes per triangle without prepared clusters) returns
+ * RM_ERR_CAPACITY and launches nothing.  All such calls on one device share
+ * that device's array: calls that overlap in time on one device (different
+ * streams or contexts) race and give undefined results; calls ordered on one
+ * stream are safe, since each clears what it needs before use. */
+int rm_align_cost_grad_noalloc(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t n_scans,
+                               const int32_t* pose_off, const double* T_wc, rm_cost_params params, double* out);
+
 /* Table I with reweighted cells (Sec. IV-C suggests adjusting the weights of
  * the penalties and rewards of the classifications): for each of P result
  * records of rm_align_cost / rm_align_cost_grad,

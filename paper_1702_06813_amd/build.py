@@ -11,7 +11,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "librendermap.so"
-SOURCES = ["rm_api.cpp", "rm_mesh.hip", "rm_raster.hip", "rm_optim.hip", "rm_icp.hip"]
+SOURCES = ["rm_api.cpp", "rm_mesh.hip", "rm_raster.hip", "rm_optim.hip", "rm_icp.hip", "rm_noalloc.hip"]
 MB_LIB = PKG / "librm_microbench.so"
 MB_SOURCES = ["rm_microbench.hip"]
 

@@ -487,6 +487,8 @@ int rm::align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int
 
 int rm::ctx_fail(rm_ctx* ctx, int code, const char* msg) { return fail(ctx, code, "%s", msg); }
 
+int rm::ctx_device(const rm_ctx* ctx) { return ctx->device; }
+
 namespace {
 
 }  // namespace
@@ -505,6 +507,7 @@ int rm_ctx_create(int32_t device, rm_ctx** out) {
     rm_ctx* c = new rm_ctx();
     c->device = device;
     DeviceGuard g(device);
+    noalloc_setup(device);
     if (hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(nullptr, RM_ERR_DEVICE, "hipHostMalloc failed");

@@ -145,5 +145,10 @@ int align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int32_t
                  const Arena* arena);
 // Records an error message on the context and returns code.
 int ctx_fail(rm_ctx* ctx, int code, const char* msg);
+// Device of a context.
+int ctx_device(const rm_ctx* ctx);
+// Finds the allocation-free scratch array's address on `device` (current);
+// called once per device by rm_ctx_create.
+void noalloc_setup(int device);
 
 }  // namespace rm

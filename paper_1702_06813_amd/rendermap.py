@@ -32,6 +32,7 @@ ABI_SYMBOLS = [
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
     "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract", "rm_depth_downsample",
     "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad", "rm_table_cost_weighted", "rm_set_bin_cap",
+    "rm_align_cost_grad_noalloc",
 ]
 TABLE_WEIGHTS = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)   # Table I as printed: reproduces E_TABLE
 
@@ -98,6 +99,8 @@ def load_library(path: Path | str | None = None):
             "rm_render_depth": [V, ctypes.POINTER(CMesh), CCamera, V, I32, V, V, V],
             "rm_align_cost": [V, ctypes.POINTER(CMesh), ctypes.POINTER(CScan), I32, V, V, CCostParams, V],
             "rm_align_cost_grad": [V, ctypes.POINTER(CMesh), ctypes.POINTER(CScan), I32, V, V, CCostParams, V],
+            "rm_align_cost_grad_noalloc": [V, ctypes.POINTER(CMesh), ctypes.POINTER(CScan), I32, V, V, CCostParams,
+                                           V],
             "rm_gn_step": [V, V, I32, D, V, V],
             "rm_adam_step": [V, V, I32, D, D, D, I32, V, V, V],
             "rm_se3_retract": [V, V, V, I32, V],
@@ -417,6 +420,15 @@ def _per_pose(t, P, n, dtype, name, dev):
     if tuple(t.shape) != (P, n):
         raise ValueError(f"{name} must be [{P}, {n}], got {tuple(t.shape)}")
     return t
+
+
+def align_cost_grad_noalloc(mesh, scans, T_wc, out, eps=0.1, poses_per_scan=None):
+    """rm_align_cost_grad_noalloc: rm_align_cost_grad with its scratch in the
+    library's fixed device array (no allocation by the library); `out`
+    ([P, 48] f64) must be given."""
+    if out is None:
+        raise ValueError("out must be given")
+    return _align("rm_align_cost_grad_noalloc", mesh, scans, poses_per_scan, T_wc, eps, out)
 
 
 def gn_step(out: torch.Tensor, T_wc: torch.Tensor, lam: float = 0.0, delta_out=None):
