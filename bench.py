@@ -129,38 +129,75 @@ def cpu_baseline(w, torch, n_poses=2):
                       f"({t:.1f} s wall)"}
 
 
-def alignment_comparison(rm, torch, w, mesh, scan, T0, n_plain=3, reps=3):
-    """Scans aligned per second: the batched gradient form (all poses of one
-    launch, 20 Gauss-Newton iterations with the eps schedule, replayed from
-    one captured hipGraph) against the paper's plain form (one pose per
-    launch, cost only, derivative-free hybrid optimizer, 700 evaluations),
-    each from the same 10 cm / 5 deg starts, with final pose errors; and the
-    paper's optimizer run for all starts in lockstep (one batched launch per
-    round of evaluations)."""
+def alignment_comparison(rm, torch, w, mesh, scan, T0, n_plain=16, reps=3):
+    """Scans aligned per second on the differentiation workload, each from
+    the same 10 cm / 5 deg starts, with final pose errors:
+      * the batched gradient forms: all 64 starts in one launch per
+        iteration, 20 iterations with the eps schedule, replayed from one
+        captured hipGraph, Gauss-Newton (LM) and Adam;
+      * the paper's plain form (one pose per launch, cost only, the
+        derivative-free hybrid optimizer, up to 700 evaluations) on n_plain
+        starts, and the same optimizer with the independent points of one
+        alignment evaluated together (same poses, fewer launches);
+      * the paper's optimizer for all 64 starts in lockstep (one launch per
+        round of evaluations over every start; the starts already fill the
+        launch, so speculative batches would only add evaluations);
+      * the ablation of the gradient form with one pose per launch, no graph
+        and one workgroup per item (no persistent scheduling)."""
     from paper_1702_06813_amd import align as A
     B = T0.shape[0]
-    al = A.BatchedAligner(mesh, scan, B, iters=20)
-    al.run(T0, use_graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        Tb = al.run(T0, use_graph=True)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
-    dtb, dab = A.pose_errors(Tb.cpu().numpy(), w.T_true)
-    log(f"batched: {B} scans in {tb * 1e3:.1f} ms; median error {np.median(dtb) * 100:.2f} cm "
-        f"{np.degrees(np.median(dab)):.3f} deg")
-    Tp, evs = [], []
-    t0 = time.perf_counter()
-    for k in range(n_plain):
-        T, e, ev = A.plain_align(mesh, scan, w.poses[k], eps=0.1, budget=700)
-        Tp.append(T); evs.append(ev)
-    tp = (time.perf_counter() - t0) / n_plain
-    dtp, dap = A.pose_errors(np.stack(Tp), w.T_true)
+    res = {}
     d0, a0 = A.pose_errors(w.poses, w.T_true)
-    log(f"plain: {n_plain} scans, {tp * 1e3:.1f} ms each; median error {np.median(dtp) * 100:.2f} cm "
-        f"{np.degrees(np.median(dap)):.3f} deg")
-    # the paper's optimizer for all B starts in lockstep, one batched launch per round
+    res["initial_error_m_median"] = float(np.median(d0))
+    res["initial_error_deg_median"] = float(np.degrees(np.median(a0)))
+    for method in ("gn", "adam"):
+        al = A.BatchedAligner(mesh, scan, B, iters=20, method=method)
+        al.run(T0, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Tb = al.run(T0, use_graph=True)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        dtb, dab = A.pose_errors(Tb.cpu().numpy(), w.T_true)
+        log(f"batched {method}: {B} scans in {tb * 1e3:.1f} ms; median error {np.median(dtb) * 100:.2f} cm "
+            f"{np.degrees(np.median(dab)):.3f} deg")
+        key = "batched" if method == "gn" else "batched_adam"
+        res[f"{key}_scans_per_s"] = B / tb
+        res[f"{key}_error_m_median"] = float(np.median(dtb))
+        res[f"{key}_error_deg_median"] = float(np.degrees(np.median(dab)))
+        if method == "gn":
+            res["batched_error_m_same_starts"] = float(np.median(dtb[:n_plain]))
+            res["batched_error_deg_same_starts"] = float(np.degrees(np.median(dab[:n_plain])))
+            tgn = tb
+    res["iterations"] = 20
+    # the paper's plain form, one evaluation per launch, and batched within each alignment
+    for form in ("plain", "plain_within"):
+        Tp, evs, nl = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_plain):
+            if form == "plain":
+                T, e, ev = A.plain_align(mesh, scan, w.poses[k], eps=0.1, budget=700)
+                nl.append(ev)
+            else:
+                T, e, ev, launches = A.plain_align_batched(mesh, scan, w.poses[k], eps=0.1, budget=700)
+                nl.append(launches)
+            Tp.append(T); evs.append(ev)
+        tp = (time.perf_counter() - t0) / n_plain
+        dtp, dap = A.pose_errors(np.stack(Tp), w.T_true)
+        log(f"{form}: {n_plain} scans, {tp * 1e3:.1f} ms each, {np.mean(nl):.0f} launches each; median error "
+            f"{np.median(dtp) * 100:.2f} cm {np.degrees(np.median(dap)):.3f} deg")
+        res[f"{form}_scans_per_s"] = 1.0 / tp
+        res[f"{form}_launches_mean"] = float(np.mean(nl))
+        res[f"{form}_evaluations_mean"] = float(np.mean(evs))
+        res[f"{form}_error_m_median"] = float(np.median(dtp))
+        res[f"{form}_error_deg_median"] = float(np.degrees(np.median(dap)))
+        if form == "plain":
+            tplain = tp
+    res["n_plain_scans"] = n_plain
+    res["speedup_vs_plain"] = tplain * B / tgn
+    # the paper's optimizer for all B starts in lockstep, speculative batches
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Tq, _, evq, launches = A.batched_plain_align(mesh, scan, w.poses, eps=0.1, budget=700)
@@ -168,16 +205,115 @@ def alignment_comparison(rm, torch, w, mesh, scan, T0, n_plain=3, reps=3):
     dtq, daq = A.pose_errors(Tq, w.T_true)
     log(f"batched plain form: {B} scans in {tq:.2f} s ({launches} launches); median error "
         f"{np.median(dtq) * 100:.2f} cm {np.degrees(np.median(daq)):.3f} deg")
-    return {"batched_scans_per_s": B / tb, "plain_scans_per_s": 1.0 / tp, "speedup_vs_plain": tp * B / tb,
-            "batched_plain_form_scans_per_s": B / tq, "batched_plain_form_launches": int(launches),
-            "batched_plain_form_error_m_median": float(np.median(dtq)),
-            "batched_plain_form_error_deg_median": float(np.degrees(np.median(daq))),
-            "iterations": 20, "plain_evaluations_mean": float(np.mean(evs)), "n_plain_scans": n_plain,
-            "initial_error_m_median": float(np.median(d0)), "initial_error_deg_median": float(np.degrees(np.median(a0))),
-            "batched_error_m_median": float(np.median(dtb)), "batched_error_deg_median": float(np.degrees(np.median(dab))),
-            "plain_error_m_median": float(np.median(dtp)), "plain_error_deg_median": float(np.degrees(np.median(dap))),
-            "batched_error_m_same_starts": float(np.median(dtb[:n_plain])),
-            "batched_error_deg_same_starts": float(np.degrees(np.median(dab[:n_plain])))}
+    res.update({"batched_plain_form_scans_per_s": B / tq, "batched_plain_form_launches": int(launches),
+                "batched_plain_form_error_m_median": float(np.median(dtq)),
+                "batched_plain_form_error_deg_median": float(np.degrees(np.median(daq)))})
+    # ablation: the gradient form with one pose per launch, eager, one workgroup per item
+    ctx = rm.context(T0.device)
+    ctx.set_schedule(1)
+    try:
+        n_abl = 8
+        al1 = A.BatchedAligner(mesh, scan, 1, iters=20)
+        al1.run(T0[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ta = [al1.run(T0[k:k + 1]).clone() for k in range(n_abl)]
+        torch.cuda.synchronize()
+        ta = (time.perf_counter() - t0) / n_abl
+    finally:
+        ctx.set_schedule(0)
+    dta, daa = A.pose_errors(torch.cat(Ta).cpu().numpy(), w.T_true)
+    log(f"one pose per launch (gradient, eager): {ta * 1e3:.1f} ms per scan; median error "
+        f"{np.median(dta) * 100:.2f} cm")
+    res.update({"one_pose_per_launch_grad_scans_per_s": 1.0 / ta,
+                "one_pose_per_launch_grad_error_m_median": float(np.median(dta)),
+                "batched_vs_one_pose_per_launch": ta * B / tgn})
+    return res
+
+
+def config_throughput(rm, torch, dev, name, steps=10):
+    """Pose-evals/s of one more workload: tiny (64x48, ~2.4k triangles, one
+    pose, cost only), kinect (640x480, ~186k triangles, 64 poses, cost only)
+    or wide (1280x960, ~4M triangles, 256 poses, cost + gradient, tile
+    autotuned).  Inputs resident before timing; W = 3 warm-up calls (the
+    first sizes the bins, and for wide runs the autotuner)."""
+    from workloads import configs
+    t0 = time.time()
+    w = getattr(configs, name)()
+    if w.map_mesh is not None:
+        mesh = rm.Mesh.from_arrays(*w.map_mesh, device=dev).prepare()
+    else:
+        parts = [rm.mesh_from_range(torch.from_numpy(d).to(dev), w.cam, T, w.stride, w.z_min, w.z_max, w.max_edge,
+                                    w.smooth_radius) for T, d in zip(w.views, w.view_depths)]
+        mesh = rm.Mesh.concat(parts).prepare()
+    scan = rm.scan_image(torch.from_numpy(w.scan_depth).to(dev), w.z_min, w.z_max, cam=w.cam)
+    T = torch.from_numpy(np.ascontiguousarray(w.poses.reshape(-1, 12))).to(dev)
+    grad = name == "wide"
+    f = rm.align_cost_grad if grad else rm.align_cost
+    ctx = rm.context(dev)
+    ctx.autotune(name == "wide")
+    out = torch.empty((T.shape[0], rm.OUT_STRIDE), dtype=torch.float64, device=dev)
+    try:
+        for _ in range(3):
+            f(mesh, scan, T, 0.1, out=out)
+        torch.cuda.synchronize()
+        ctx.profile(True); ctx.profile_read()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            f(mesh, scan, T, 0.1, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / steps
+        n, ms = ctx.profile_read()
+    finally:
+        ctx.profile(False)
+        ctx.autotune(False)
+    tile = ctx.get_tile(w.cam.width, w.cam.height, T.shape[0], mesh.n_tris)
+    log(f"{name}: {T.shape[0]} poses, {mesh.n_tris} triangles, {w.cam.width}x{w.cam.height}: {dt * 1e3:.3f} ms per "
+        f"call, {T.shape[0] / dt:.0f} pose-evals/s (tile {tile}, set up in {time.time() - t0:.1f}s)")
+    return {"pose_evals_per_s": T.shape[0] / dt, "ms_per_call": dt * 1e3, "raster_ms": ms / max(n, 1),
+            "poses": int(T.shape[0]), "n_tris": int(mesh.n_tris), "image": [w.cam.width, w.cam.height],
+            "mode": "cost + gradient" if grad else "cost", "tile": list(tile), "autotuned": name == "wide"}
+
+
+def trajectory_c5(rm, torch, dev, n_scans=500):
+    """Scan-to-map alignment of a 500-scan looped walk (0.5 m/s at 2 Hz, 0.25
+    m apart) through the cluttered corridor, scans cycling 320x240, 640x480
+    and 1280x960, against the ~2.2M-triangle map of 130 meshified views:
+    every scan from exactly 10 cm / 5 deg off its truth, 20 Gauss-Newton
+    iterations, 32 scans per launch, one captured graph per batch shape.
+    Timed: the whole alignment of all scans (staging copies, graph replays,
+    pose read-back); not timed: generation, meshing, the warm-up pass."""
+    from paper_1702_06813_amd import align as A
+    from workloads import configs
+    t0 = time.time()
+    tr = configs.trajectory(n_scans=n_scans)
+    parts = [rm.mesh_from_range(torch.from_numpy(d).to(dev), tr.view_cam, T, tr.stride, tr.z_min, tr.z_max,
+                                tr.max_edge, tr.smooth_radius) for T, d in zip(tr.views, tr.view_depths)]
+    mesh = rm.Mesh.concat(parts).prepare()
+    scans = [rm.scan_image(torch.from_numpy(s.depth).to(dev), tr.z_min, tr.z_max, cam=s.cam) for s in tr.scans]
+    T0 = np.stack([s.poses[0] for s in tr.scans])
+    truth = np.stack([s.T_true for s in tr.scans])
+    torch.cuda.synchronize()
+    log(f"trajectory: {len(scans)} scans, map {mesh.n_tris} triangles, set up in {time.time() - t0:.1f}s")
+    ta = A.TrajectoryAligner(mesh)
+    ta.run(scans, T0)                                  # sizes scratch and captures the graphs
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T, launches = ta.run(scans, T0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    errs = [A.pose_errors(T[j], truth[j]) for j in range(len(T))]
+    dt_m = np.array([e[0][0] for e in errs]); da = np.degrees(np.array([e[1][0] for e in errs]))
+    d0 = np.array([A.pose_errors(T0[j], truth[j])[0][0] for j in range(len(T))])
+    log(f"trajectory: {len(T) / dt:.0f} scans/s ({launches} cost launches, {len(ta.shapes)} graph shapes); RMSE "
+        f"{np.sqrt(np.mean(dt_m ** 2)) * 100:.2f} cm {np.sqrt(np.mean(da ** 2)):.3f} deg (initial "
+        f"{np.sqrt(np.mean(d0 ** 2)) * 100:.1f} cm)")
+    return {"scans": len(T), "scans_per_s": len(T) / dt, "wall_s": dt, "cost_launches": int(launches),
+            "graph_shapes": len(ta.shapes), "map_tris": int(mesh.n_tris),
+            "rmse_m": float(np.sqrt(np.mean(dt_m ** 2))), "rmse_deg": float(np.sqrt(np.mean(da ** 2))),
+            "median_error_m": float(np.median(dt_m)), "p90_error_m": float(np.percentile(dt_m, 90)),
+            "initial_rmse_m": float(np.sqrt(np.mean(d0 ** 2))),
+            "paper_context": "the paper aligns scans one second apart at about 2 Hz on a GTX 765M"}
 
 
 def icp_odometry(rm, torch, dev, n_frames=33, iters=10, reps=3):
@@ -243,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alignment", action="store_true", help="skip the batched-vs-plain alignment comparison")
     ap.add_argument("--no-icp", action="store_true", help="skip the render-accelerated ICP odometry (Sec. V)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
+    ap.add_argument("--no-trajectory", action="store_true", help="skip the 500-scan trajectory alignment")
     ap.add_argument("--atomic-peaks", action="store_true",
                     help="only run the atomic-throughput microbenchmarks (a small sweep of launch shapes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -367,6 +505,10 @@ def main():
         res["alignment"] = alignment_comparison(rm, torch, w, mesh, scan, T0)
     if not args.no_icp:
         res["icp_odometry"] = icp_odometry(rm, torch, dev)
+    if not args.no_configs:
+        res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in ("tiny", "kinect", "wide")}
+    if not args.no_trajectory:
+        res["trajectory"] = trajectory_c5(rm, torch, dev)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a pixel sample")
         res["cpu_baseline"] = cpu_baseline(w, torch)

@@ -46,11 +46,17 @@ class BatchedAligner:
     """Fixed-shape batched alignment (mesh, scans and pose count fixed), with
     optional hipGraph capture of the full iteration sequence."""
 
-    def __init__(self, mesh, scans, n_poses, iters=20, eps=(0.5, 0.1), method="gn", lam=1e-3, lr=0.01,
-                 poses_per_scan=None, device=None):
+    def __init__(self, mesh, scans, n_poses, iters=20, eps=(0.5, 0.1), method="gn", lam=1e-3, lr=(0.04, 0.002),
+                 poses_per_scan=None, device=None, betas=(0.5, 0.9)):
+        """method "gn" (Levenberg-Marquardt, damping lam) or "adam" (step size
+        lr, or (lr0, lr1) for a geometric schedule from lr0 to lr1; moment
+        decays betas).  The Adam defaults are the best of a small sweep on
+        the Kinect-like map from 10 cm / 5 deg in 20 iterations."""
         self.mesh, self.scans = mesh, scans
         self.dev = mesh.xyz.device if device is None else device
-        self.iters, self.method, self.lam, self.lr = iters, method, lam, lr
+        self.iters, self.method, self.lam = iters, method, lam
+        self.lrs = eps_schedule(iters, *lr) if isinstance(lr, (tuple, list)) else [float(lr)] * iters
+        self.betas = betas
         self.eps = eps_schedule(iters, *eps)
         self.pps = poses_per_scan
         self.T = torch.empty((n_poses, 12), dtype=torch.float64, device=self.dev)
@@ -65,7 +71,7 @@ class BatchedAligner:
             if self.method == "gn":
                 R.gn_step(self.out, self.T, self.lam)
             else:
-                R.adam_step(self.out, self.T, self.m, self.v, k + 1, self.lr)
+                R.adam_step(self.out, self.T, self.m, self.v, k + 1, self.lrs[k], *self.betas)
 
     def run(self, T0: torch.Tensor, use_graph=False):
         """Aligns every pose of T0 ([P,12] f64 on the device); returns T (in place buffer)."""
@@ -93,7 +99,58 @@ class BatchedAligner:
         return self.T
 
 
-def batched_align(mesh, scans, T0, iters=20, eps=(0.5, 0.1), method="gn", lam=1e-3, lr=0.01, poses_per_scan=None):
+class TrajectoryAligner:
+    """Scan-to-map alignment of a stream of scans of mixed resolutions: scans
+    are taken in batches of up to MAX_SCANS per launch (one pose each), every
+    batch's whole iteration sequence (cost + gradient + Gauss-Newton blocks,
+    Levenberg-Marquardt update, eps schedule) replayed from one hipGraph per
+    batch shape.  A batch's scan images are copied into fixed staging images
+    of its shape (ordered by resolution), so that the graph of a shape serves
+    every batch of that shape."""
+
+    def __init__(self, mesh, iters=20, eps=(0.5, 0.1), lam=1e-3, batch=None):
+        self.mesh = mesh
+        self.iters, self.eps, self.lam = iters, eps, lam
+        self.batch = batch or R.MAX_SCANS
+        self.shapes = {}
+
+    def _shape(self, cams):
+        key = tuple((int(c.width), int(c.height), float(c.fx), float(c.fy), float(c.cx), float(c.cy))
+                    for c in cams)
+        if key not in self.shapes:
+            dev = self.mesh.xyz.device
+            stage = [R.Scan(torch.empty((int(c.height), int(c.width)), dtype=torch.float32, device=dev),
+                            torch.empty((int(c.height), int(c.width)), dtype=torch.uint8, device=dev), c)
+                     for c in cams]
+            al = BatchedAligner(self.mesh, stage, len(cams), self.iters, self.eps, "gn", self.lam,
+                                poses_per_scan=[1] * len(cams))
+            self.shapes[key] = (stage, al)
+        return self.shapes[key]
+
+    def run(self, scans, T0, use_graph=True):
+        """scans: list of R.Scan (device scan images); T0: [N,12] or [N,3,4]
+        initial poses (host or device).  Returns [N,3,4] f64 host poses and
+        the number of launches of the cost kernel."""
+        dev = self.mesh.xyz.device
+        T0 = torch.as_tensor(np.asarray(T0, np.float64).reshape(-1, 12) if not torch.is_tensor(T0) else T0,
+                             device=dev).reshape(-1, 12)
+        out = torch.empty_like(T0)
+        launches = 0
+        for b0 in range(0, len(scans), self.batch):
+            idx = list(range(b0, min(b0 + self.batch, len(scans))))
+            idx.sort(key=lambda j: (int(scans[j].cam.height), int(scans[j].cam.width)))
+            stage, al = self._shape([scans[j].cam for j in idx])
+            for st, j in zip(stage, idx):
+                st.depth.copy_(scans[j].depth)
+                st.cls.copy_(scans[j].cls)
+            T = al.run(T0[idx], use_graph=use_graph)
+            out[idx] = T
+            launches += self.iters
+        return out.cpu().numpy().reshape(-1, 3, 4), launches
+
+
+def batched_align(mesh, scans, T0, iters=20, eps=(0.5, 0.1), method="gn", lam=1e-3, lr=(0.04, 0.002),
+                  poses_per_scan=None):
     a = BatchedAligner(mesh, scans, T0.reshape(-1, 12).shape[0], iters, eps, method, lam, lr, poses_per_scan)
     return a.run(T0).clone()
 
@@ -206,6 +263,182 @@ def _hybrid(n=6, budget=700, fd_step=(0.02, 0.02, 0.02, 0.02, 0.02, 0.02),
     return (x2, fx2, evals + e2) if fx2 <= fx else (x, fx, evals + e2)
 
 
+# ---------------------------------------------------------------------------- speculative batches
+#
+# The same optimizer asking, at each step, for every point the next decision
+# may need: each yield is a list of points and is sent the list of their
+# costs (one batched launch).  Decisions are then taken in the sequential
+# order from those costs, so the trajectory, the result and the counted
+# evaluations are exactly those of the one-point generators above; points
+# the sequential form would not have evaluated are discarded uncounted.
+#   initial gradient descent: x with its 2n-point central-difference stencil,
+#     then the six backtracking steps of the line search, then the next stencil;
+#   Nelder-Mead: the initial simplex, then per iteration the reflection, the
+#     expansion and both contractions (and the n shrink points only if needed);
+#   coordinate descent: the +/- probes of every remaining axis of the sweep at
+#     the current point, up to the first accepted probe.
+
+def _stencil(x, h):
+    pts = []
+    for i in range(len(x)):
+        e = np.zeros(len(x)); e[i] = h[i]
+        pts += [x + e, x - e]
+    return pts
+
+
+def _nelder_mead_b(x0, scale, max_evals, tol=1e-9):
+    n = len(x0)
+    pts = [np.array(x0, float)] + [np.array(x0, float) + scale[i] * np.eye(n)[i] for i in range(n)]
+    vals = list((yield list(pts)))
+    evals = n + 1
+    while evals < max_evals:
+        order = np.argsort(vals)
+        pts = [pts[i] for i in order]
+        vals = [vals[i] for i in order]
+        if abs(vals[-1] - vals[0]) <= tol and np.max(np.abs(np.array(pts[1:]) - pts[0])) <= tol:
+            break
+        c = np.mean(pts[:-1], axis=0)
+        xr = c + (c - pts[-1])
+        xe = c + 2.0 * (c - pts[-1])
+        xc_out = c + 0.5 * (xr - c)
+        xc_in = c + 0.5 * (pts[-1] - c)
+        fr, fe, fco, fci = (yield [xr, xe, xc_out, xc_in])
+        evals += 1
+        if fr < vals[0]:
+            evals += 1
+            if fe < fr:
+                pts[-1], vals[-1] = xe, fe
+            else:
+                pts[-1], vals[-1] = xr, fr
+        elif fr < vals[-2]:
+            pts[-1], vals[-1] = xr, fr
+        else:
+            xc, fc = (xc_in, fci) if fr >= vals[-1] else (xc_out, fco)
+            evals += 1
+            if fc < min(fr, vals[-1]):
+                pts[-1], vals[-1] = xc, fc
+            else:
+                shr = [pts[0] + 0.5 * (pts[i] - pts[0]) for i in range(1, len(pts))]
+                vs = yield shr
+                for i in range(1, len(pts)):
+                    pts[i], vals[i] = shr[i - 1], vs[i - 1]
+                    evals += 1
+    i = int(np.argmin(vals))
+    return pts[i], vals[i], evals
+
+
+def _coordinate_descent_b(x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
+    x, fx, evals = np.array(x0, float), f0, 0
+    step = np.array(step, float)
+    n = len(x)
+    while evals < max_evals and np.any(step > min_step):
+        i = 0
+        while i < n:
+            axes = [k for k in range(i, n) if step[k] > min_step]
+            if not axes:
+                break
+            probes = []
+            for k in axes:
+                for sgn in (+1.0, -1.0):
+                    y = x.copy(); y[k] += sgn * step[k]
+                    probes.append(y)
+            v = yield probes
+            i = n                                  # the sweep ends unless a probe is accepted
+            for j, k in enumerate(axes):
+                accepted = False
+                for s in range(2):
+                    evals += 1
+                    if v[2 * j + s] < fx:
+                        x, fx = probes[2 * j + s], v[2 * j + s]
+                        accepted = True
+                        break
+                if not accepted:
+                    step[k] *= shrink
+                if evals >= max_evals:
+                    break
+                if accepted:
+                    i = k + 1                      # later axes from the new point
+                    break
+            if evals >= max_evals:
+                break
+    return x, fx, evals
+
+
+def _hybrid_b(n=6, budget=700, fd_step=(0.02, 0.02, 0.02, 0.02, 0.02, 0.02),
+              simplex=(0.05, 0.05, 0.05, 0.05, 0.05, 0.05), gd_iters=2, nm_share=0.6):
+    """_hybrid asking for points in speculative batches (same result)."""
+    x = np.zeros(n)
+    h = np.asarray(fd_step, float)
+    first = yield [x] + _stencil(x, h)
+    fx = first[0]
+    evals = 1
+    for it in range(gd_iters):
+        v = first[1:] if it == 0 else (yield _stencil(x, h))
+        g = np.zeros(n)
+        for i in range(n):
+            g[i] = (v[2 * i] - v[2 * i + 1]) / (2 * h[i])
+            evals += 2
+        gn = np.linalg.norm(g / h)
+        if gn == 0:
+            break
+        d = -(g / h) / gn * h * 4.0
+        ys, t = [], 1.0
+        for _ in range(6):
+            ys.append(x + t * d)
+            t *= 0.5
+        vy = yield ys
+        for y, fy in zip(ys, vy):
+            evals += 1
+            if fy < fx:
+                x, fx = y, fy
+                break
+    x, fx, e1 = yield from _nelder_mead_b(x, np.asarray(simplex, float), int((budget - evals) * nm_share) + evals)
+    evals += e1
+    x2, fx2, e2 = yield from _coordinate_descent_b(x, fx, np.asarray(simplex, float) * 0.25, budget - evals)
+    return (x2, fx2, evals + e2) if fx2 <= fx else (x, fx, evals + e2)
+
+
+def _drive_b(gen, f):
+    """Drives a batch generator with f(list of points) -> list of costs;
+    returns (result, batches)."""
+    batches = 0
+    try:
+        pts = next(gen)
+        while True:
+            batches += 1
+            pts = gen.send([float(v) for v in f(pts)])
+    except StopIteration as stop:
+        return stop.value, batches
+
+
+def hybrid_minimize_batched(f_batch, n=6, budget=700, **kw):
+    """The hybrid optimizer with speculative batches: f_batch(list of points)
+    returns their costs.  Returns (x, fx, evals, batches), (x, fx, evals)
+    equal to hybrid_minimize's."""
+    (x, fx, ev), nb = _drive_b(_hybrid_b(n, budget, **kw), f_batch)
+    return x, fx, ev, nb
+
+
+def lockstep_batches(gens, evaluate):
+    """lockstep for batch generators: each round, evaluate(ks, lists of
+    points) receives the unfinished instances and their batches and returns
+    one list of costs per instance.  Returns (results, rounds)."""
+    pending = [next(g) for g in gens]
+    result = [None] * len(gens)
+    rounds = 0
+    while True:
+        act = [k for k in range(len(gens)) if result[k] is None]
+        if not act:
+            return result, rounds
+        vals = evaluate(act, [pending[k] for k in act])
+        rounds += 1
+        for k, v in zip(act, vals):
+            try:
+                pending[k] = gens[k].send([float(x) for x in v])
+            except StopIteration as stop:
+                result[k] = stop.value
+
+
 def _drive(gen, f):
     try:
         x = next(gen)
@@ -228,6 +461,28 @@ def coordinate_descent(f, x0, f0, step, max_evals, shrink=0.5, min_step=1e-4):
 def hybrid_minimize(f, n=6, budget=700, **kw):
     """The paper's hybrid optimizer on f from x = 0; returns (x, fx, evals)."""
     return _drive(_hybrid(n, budget, **kw), f)
+
+
+def plain_align_batched(mesh, scan, T0, eps=0.1, budget=700, weights=None):
+    """The paper's optimizer for one alignment with its independent points
+    evaluated together: every batch of the speculative hybrid optimizer (the
+    finite-difference stencil, the line-search steps, the initial simplex,
+    the Nelder-Mead candidates, the coordinate-descent probes) is one
+    rm_align_cost launch.  Same trajectory, pose, cost and evaluation count
+    as plain_align.  Returns (T [3,4] numpy, E, evaluations, launches)."""
+    dev = mesh.xyz.device
+    T0d = torch.as_tensor(np.asarray(T0, np.float64).reshape(1, 12), device=dev)
+
+    def f(xs):
+        X = torch.from_numpy(np.stack(xs)).to(dev)
+        Td = R.se3_retract(T0d.expand(len(xs), 12).contiguous(), X)
+        out = R.align_cost(mesh, scan, Td, eps)
+        v = out[:, R.OUT_E_TABLE] if weights is None else R.table_cost_weighted(out, weights)
+        return v.cpu().numpy()
+
+    x, fx, evals, launches = hybrid_minimize_batched(f, budget=budget)
+    xd = torch.from_numpy(np.asarray(x, np.float64).reshape(1, 6)).to(dev)
+    return R.se3_retract(T0d, xd).cpu().numpy().reshape(3, 4), fx, evals, launches
 
 
 def plain_align(mesh, scan, T0, eps=0.1, budget=700, weights=None):
@@ -276,13 +531,16 @@ def lockstep(gens, evaluate):
                 result[k] = stop.value
 
 
-def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weights=None):
+def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weights=None, speculative=False):
     """The paper's optimizer for many alignments at once: every instance runs
     the same hybrid optimizer as plain_align, and each round evaluates the
     next point of every unfinished instance in one launch (T0: [K,3,4] or
     [K,12] host poses; scans: one scan, or a list with scan_of[k] the scan of
     instance k).  Each instance evaluates exactly the points plain_align
-    would.  Returns (T [K,3,4] numpy, E [K], evaluations [K], launches)."""
+    would.  With speculative=True every instance contributes its whole
+    speculative batch (plain_align_batched) to each round's launch: fewer
+    launches, same results.  Returns (T [K,3,4] numpy, E [K], evaluations
+    [K], launches)."""
     dev = mesh.xyz.device
     T0 = np.asarray(T0, np.float64).reshape(-1, 12)
     K = T0.shape[0]
@@ -305,7 +563,19 @@ def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weig
         res[order] = v
         return res
 
-    result, launches = lockstep([_hybrid(budget=budget) for _ in range(K)], evaluate)
+    if speculative:
+        def evaluate_b(ks, batches):
+            # every point of every active instance's batch in one launch
+            flat_k = [k for k, b in zip(ks, batches) for _ in b]
+            flat_x = [x for b in batches for x in b]
+            v = evaluate(flat_k, flat_x)
+            out, o = [], 0
+            for b in batches:
+                out.append(v[o:o + len(b)]); o += len(b)
+            return out
+        result, launches = lockstep_batches([_hybrid_b(budget=budget) for _ in range(K)], evaluate_b)
+    else:
+        result, launches = lockstep([_hybrid(budget=budget) for _ in range(K)], evaluate)
     X = torch.from_numpy(np.stack([r[0] for r in result])).to(dev)
     T = R.se3_retract(T0d, X).cpu().numpy().reshape(K, 3, 4)
     return T, np.array([r[1] for r in result]), np.array([r[2] for r in result]), launches

@@ -103,3 +103,45 @@ def test_adam_converges_on_quadratic_bowl(oracle_mod):
         d, m, v = O.adam_step(A @ (x - c), m, v, k, lr=lr_k)
         x = x + d
     assert np.abs(x - c).max() < 1e-3, x - c
+
+
+# ---------------------------------------------------------------- speculative batches of the paper's optimizer
+
+def _cases():
+    rng = np.random.default_rng(7)
+    cs = [rng.normal(scale=0.03, size=6) for _ in range(4)]
+    fs = [lambda x, c=c: float(np.floor(2e4 * np.sum((x - c) ** 2))) for c in cs]          # plateaus like E(X)
+    fs.append(lambda x: float(np.sum(100 * (x[1:] - x[:-1] ** 2) ** 2 + (1 - x[:-1]) ** 2)))  # Rosenbrock
+    fs.append(lambda x: float(np.floor(50 * np.sum(np.abs(x - 0.01)))))                       # coarse plateaus
+    fs.append(lambda x: 0.0)                                                                   # flat: zero gradient
+    return fs
+
+
+def test_speculative_batches_reproduce_the_sequential_optimizer():
+    """The batch form of the hybrid optimizer (stencil, line search, simplex,
+    Nelder-Mead candidates and coordinate-descent probes requested together)
+    ends at exactly the point, cost and evaluation count of the one-point
+    form, for costs with plateaus, a smooth valley and a flat cost, under
+    budgets that stop it in each phase; it needs far fewer batches than
+    evaluations."""
+    for f in _cases():
+        for budget in (30, 57, 120, 333, 700):
+            x1, f1, e1 = A.hybrid_minimize(f, budget=budget)
+            x2, f2, e2, nb = A.hybrid_minimize_batched(lambda xs: [f(x) for x in xs], budget=budget)
+            np.testing.assert_array_equal(x1, x2)
+            assert f1 == f2 and e1 == e2, (budget, e1, e2)
+            assert nb <= e1
+    f = _cases()[0]
+    _, _, ev, nb = A.hybrid_minimize_batched(lambda xs: [f(x) for x in xs], budget=700)
+    assert nb < ev / 3, (nb, ev)
+
+
+def test_lockstep_of_speculative_batches_equals_one_at_a_time():
+    fs = _cases()[:5]
+    alone = [A.hybrid_minimize(f, budget=300) for f in fs]
+    res, rounds = A.lockstep_batches([A._hybrid_b(budget=300) for _ in fs],
+                                     lambda ks, bs: [[fs[k](x) for x in b] for k, b in zip(ks, bs)])
+    for (x1, f1, e1), (x2, f2, e2) in zip(alone, res):
+        np.testing.assert_array_equal(x1, x2)
+        assert f1 == f2 and e1 == e2
+    assert rounds < max(e for _, _, e in alone)

@@ -166,6 +166,80 @@ def uneven(seed: int = 5, n_views: int = 56, n_scans: int = 32) -> Stream:
     return Stream("uneven", scene, S.QVGA, views, depths, scans)
 
 
+def _loop_pose(scene, s, frac=0.75, phase=0.0):
+    """Sensor on a looped walk around the inside of a room: along the ellipse
+    at ``frac`` of the room's half extents (``s`` = arc length, periodic),
+    looking inward at a point that wanders around the room centre, with the
+    height and pitch varying slowly so that successive laps differ."""
+    c = _room_center(scene)
+    a, b = frac * 0.5 * (scene.room_hi[0] - scene.room_lo[0]), frac * 0.5 * (scene.room_hi[1] - scene.room_lo[1])
+    # arc length of the ellipse by Ramanujan's approximation of its perimeter
+    per = np.pi * (3 * (a + b) - np.sqrt((3 * a + b) * (a + 3 * b)))
+    ang = 2 * np.pi * (s / per)
+    pos = np.array([c[0] + a * np.cos(ang), c[1] + b * np.sin(ang), 1.45 + 0.25 * np.sin(s / 7.3 + phase)])
+    tgt = c[:2] + 0.6 * np.array([np.sin(s / 5.1 + phase), np.cos(s / 6.7 + phase)])
+    yaw = np.arctan2(tgt[1] - pos[1], tgt[0] - pos[0])
+    return S.look_pose(pos, yaw, np.deg2rad(-22.0 + 10.0 * np.sin(s / 4.3 + phase)))
+
+
+def _range_images(jobs, workers=None):
+    """Range images of (scene, cam, T, seed, kwargs) jobs, in a process pool."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    n = workers or min(16, os.cpu_count() or 1)
+    if n <= 1 or len(jobs) < 8:
+        return [S.range_image(sc, cam, T, seed, **kw) for sc, cam, T, seed, kw in jobs]
+    with ProcessPoolExecutor(max_workers=n) as ex:
+        futs = [ex.submit(S.range_image, sc, cam, T, seed, **kw) for sc, cam, T, seed, kw in jobs]
+        return [f.result() for f in futs]
+
+
+@dataclass
+class Trajectory:
+    """A sensor walking a loop through a mapped scene: the map views and, for
+    every scan, its ground truth, range image and initial pose estimate."""
+    name: str
+    scene: S.Scene
+    view_cam: S.Camera
+    views: list
+    view_depths: list
+    scans: list                        # StreamScan, poses = [1,3,4] initial estimate
+    stride: int = 6
+    max_edge: float = 0.1 * 6 / 2
+    smooth_radius: int = 4
+    z_min: float = 0.5
+    z_max: float = 8.0
+
+
+def trajectory(seed: int = 6, n_scans: int = 500, spacing: float = 0.25, init=(0.10, 5.0),
+               workers=None) -> Trajectory:
+    """Scan-to-map alignment along a looped walk: an 8 x 6 x 2.8 m office room
+    with 24 boxes and a doorway; map = 130 Kinect-like views spread over one
+    lap of the walk, meshified at stride 6 with node smoothing radius 4
+    (130 x 16,748 = 2,177,240 triangles, free-occupied plus free-unknown);
+    ``n_scans`` scans ``spacing`` m apart along the loop (0.5 m/s at 2 Hz,
+    about 7.5 laps of ~16.6 m for 500 scans), cycling 320x240, 640x480 and
+    1280x960, each starting exactly init[0] m and init[1] degrees from its
+    truth in random directions."""
+    door = S.Door(axis=0, side=1, lo=(2.0, 0.0), hi=(3.0, 2.1))
+    scene = S.random_box_room(seed, (8.0, 6.0, 2.8), 24, doors=[door])
+    a, b = 0.75 * 4.0, 0.75 * 3.0
+    per = np.pi * (3 * (a + b) - np.sqrt((3 * a + b) * (a + 3 * b)))
+    views = [_loop_pose(scene, per * (k + 0.5) / 130, phase=0.9 * k) for k in range(130)]
+    rng = np.random.default_rng(seed)
+    cams = (S.QVGA, S.KINECT, S.WIDE)
+    truths = [_loop_pose(scene, 0.3 + j * spacing, phase=0.0) for j in range(n_scans)]
+    kw = dict(noise_rel=0.01, dropout=0.02)
+    jobs = [(scene, S.KINECT, T, seed * 1000 + k, kw) for k, T in enumerate(views)]
+    jobs += [(scene, cams[j % 3], T, seed * 100000 + j, kw) for j, T in enumerate(truths)]
+    imgs = _range_images(jobs, workers)
+    scans = []
+    for j, T in enumerate(truths):
+        T0 = S.perturb(T, rng, init[0], np.deg2rad(init[1]), fixed=True)
+        scans.append(StreamScan(cams[j % 3], T, imgs[len(views) + j], T0[None]))
+    return Trajectory("trajectory", scene, S.KINECT, views, imgs[:len(views)], scans)
+
+
 @dataclass
 class Sequence:
     """A sensor moving through a scene: ground-truth poses and range images,

@@ -215,18 +215,33 @@ def analytic_depth(scene: Scene, cam: Camera, T: np.ndarray, z_cut=np.inf) -> np
                 inside = ((p[..., other] >= d.lo[0]) & (p[..., other] <= d.hi[0]) &
                           (p[..., 2] >= d.lo[1]) & (p[..., 2] <= d.hi[1]))
                 depth = np.where(on_wall & inside, np.inf, depth)
+        H, W = depth.shape
         for lo, hi in scene.boxes:
             corners = np.array([[lo[0] if i & 1 else hi[0], lo[1] if i & 2 else hi[1], lo[2] if i & 4 else hi[2]]
                                 for i in range(8)])
-            zc = (corners - o) @ T[:, 2]
+            cc = (corners - o) @ T[:, :3]                  # camera-frame corners
+            zc = cc[:, 2]
             if zc.max() <= 0.0 or zc.min() > z_cut:
                 continue
-            t1 = (lo - o) * inv
-            t2 = (hi - o) * inv
+            # pixels whose ray can meet the box: with every corner in front
+            # of the camera, inside the rectangle of the projected corners
+            # (one pixel of margin); otherwise the whole image
+            r0, r1, c0, c1 = 0, H, 0, W
+            if zc.min() > 1e-9:
+                u = cam.fx * cc[:, 0] / zc + cam.cx
+                v = cam.fy * cc[:, 1] / zc + cam.cy
+                c0, c1 = max(0, int(np.floor(u.min())) - 1), min(W, int(np.ceil(u.max())) + 2)
+                r0, r1 = max(0, int(np.floor(v.min())) - 1), min(H, int(np.ceil(v.max())) + 2)
+                if c0 >= c1 or r0 >= r1:
+                    continue
+            sub = (slice(r0, r1), slice(c0, c1))
+            t1 = (lo - o) * inv[sub]
+            t2 = (hi - o) * inv[sub]
             tn = np.nanmax(np.minimum(t1, t2), axis=-1)
             tf = np.nanmin(np.maximum(t1, t2), axis=-1)
             hit = (tn <= tf) & (tn > 0)
-            depth = np.where(hit & (tn < depth), tn, depth)
+            d = depth[sub]
+            depth[sub] = np.where(hit & (tn < d), tn, d)
     return depth
 
 
