@@ -428,6 +428,7 @@ def main():
 
     ctx.profile(True)
     ctx.profile_read()
+    ctx.profile_read_binning()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -435,6 +436,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_launch, raster_ms = ctx.profile_read()
+    n_bin, bin_ms = ctx.profile_read_binning()
     ctx.profile(False)
     wall = t1 - t0
     log(f"timed {args.steps} steps in {wall * 1e3:.1f} ms; rasterizer {n_launch} launches, {raster_ms:.2f} ms")
@@ -447,6 +449,9 @@ def main():
     bytes_launch = float(np.sum(12.0 * v_per_t * t_vis + 13.0 * t_vis + 5.0 * W * H + 8 * 3 + 4 * 9 + 4 * 34))
     avg_s = raster_ms / max(n_launch, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
+    # the binning pass reads the visible mesh once per pose (indices and vertices)
+    bin_bytes = float(np.sum(12.0 * v_per_t * t_vis + 12.0 * t_vis))
+    bin_s = bin_ms / max(n_bin, 1) / 1e3
 
     # the same step replayed from one captured hipGraph
     T.copy_(T0)
@@ -486,7 +491,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(tile),
                      "valu_issue_frac_profiled": profiled_traffic(tile, "valu_issue_frac"),
                      "kernel": "k_raster (grad)", "avg_launch_ms": avg_s * 1e3,
-                     "bytes_per_launch": bytes_launch, "visible_tris_per_pose": float(t_vis.mean())},
+                     "bytes_per_launch": bytes_launch, "visible_tris_per_pose": float(t_vis.mean()),
+                     "k_bin": {"avg_launch_ms": bin_s * 1e3, "bytes_per_launch": bin_bytes,
+                               "achieved": bin_bytes / bin_s / 1e9, "frac": bin_bytes / bin_s / 1e9 / HBM_PEAK_GBS,
+                               "traffic": profiled_traffic(tile, "bin_bytes_per_launch"),
+                               "note": "algorithmic bytes: the visible mesh (12 B per vertex, 12 B of indices "
+                                       "per triangle) once per pose"}},
         "graph_ms_per_step": graph_ms,
         "atomics": atomic_peaks(),
     }

@@ -217,12 +217,17 @@ int rm_get_tile(rm_ctx* ctx, int32_t width, int32_t height, int32_t n_poses, int
 
 /* Kernel timing for reports.  While enabled, every launch of the tile
  * rasterizer (the kernel that rasterizes, compares and reduces) is bracketed
- * by HIP events on the context stream; launches recorded into a stream
- * capture are not timed.  rm_profile_read synchronizes the context stream,
- * returns the number of timed launches and their summed duration in
- * milliseconds, and clears the record. */
+ * by HIP events on the context stream, and so is every launch of the
+ * binning kernel; launches recorded into a stream capture or made by
+ * rm_align_cost_grad_noalloc are not timed.  rm_profile_read synchronizes
+ * the context stream, returns the number of timed rasterizer launches and
+ * their summed duration in milliseconds, and clears that record. */
 int rm_profile(rm_ctx* ctx, int32_t enable);
 int rm_profile_read(rm_ctx* ctx, int64_t* n_launches, double* total_ms);
+/* As rm_profile_read, for the launches of the binning kernel (the pass that
+ * sorts each pose's visible triangles into per-screen-tile bins before the
+ * rasterizer); the two records are kept and cleared separately. */
+int rm_profile_read_binning(rm_ctx* ctx, int64_t* n_launches, double* total_ms);
 
 /* ---------------------------------------------------------------- graphs */
 

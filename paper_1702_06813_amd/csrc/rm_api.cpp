@@ -34,8 +34,9 @@ struct rm_ctx {
     std::map<std::vector<int64_t>, std::pair<int, int>> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
-    size_t prof_used = 0;
+    // timed launches of the rasterizer ([0]) and of the binning kernel ([1])
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[2];
+    size_t prof_used[2] = {0, 0};
     // tile-bin capacity, adapted from the largest bin of earlier calls, unless
     // fixed by rm_set_bin_cap (then never grown: overflowing bins take the
     // every-cluster path)
@@ -220,6 +221,24 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
     ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
 }
 
+// Starts the timing of one launch of kernel k (0 rasterizer, 1 binning) when
+// profiling (not under capture or for the allocation-free call); *stop
+// receives the event to record after it, or null.
+int prof_begin(rm_ctx* ctx, int k, bool fixed, hipEvent_t* stop) {
+    *stop = nullptr;
+    if (!ctx->profiling || capturing(ctx) || fixed) return RM_OK;
+    if (ctx->prof_used[k] == ctx->prof_events[k].size()) {
+        hipEvent_t x, y;
+        RM_HIP(ctx, hipEventCreate(&x));
+        RM_HIP(ctx, hipEventCreate(&y));
+        ctx->prof_events[k].emplace_back(x, y);
+    }
+    RM_HIP(ctx, hipEventRecord(ctx->prof_events[k][ctx->prof_used[k]].first, ctx->stream));
+    *stop = ctx->prof_events[k][ctx->prof_used[k]].second;
+    ++ctx->prof_used[k];
+    return RM_OK;
+}
+
 // One scoring pass: cull, near-to-far cluster order, bin, rasterize (+ fused
 // comparison), reduce.
 int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
@@ -326,7 +345,11 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.depth_out = depth_out;
         a.tri_out = tri_out;
         a.cls_out = cls_out;
+        hipEvent_t be1;
+        int prc = prof_begin(ctx, 1, arena.fixed != nullptr, &be1);
+        if (prc) return prc;
         RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
+        if (be1) RM_HIP(ctx, hipEventRecord(be1, ctx->stream));
         if (persistent) {
             int32_t* order = reinterpret_cast<int32_t*>(at(o_ord));
             RM_HIP(ctx, launch_order(ctx->stream, bd, bin_small, bin_big, R, hist, order));
@@ -345,17 +368,10 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         if (grown <= cap) break;               // cannot grow: overflowing bins take the slow path
         ctx->bin_cap = (int32_t)std::max<int64_t>(grown, ctx->bin_cap);
     }
-    hipEvent_t pe1 = nullptr;
-    if (ctx->profiling && !capturing(ctx) && !arena.fixed) {
-        if (ctx->prof_used == ctx->prof_events.size()) {
-            hipEvent_t x, y;
-            RM_HIP(ctx, hipEventCreate(&x));
-            RM_HIP(ctx, hipEventCreate(&y));
-            ctx->prof_events.emplace_back(x, y);
-        }
-        RM_HIP(ctx, hipEventRecord(ctx->prof_events[ctx->prof_used].first, ctx->stream));
-        pe1 = ctx->prof_events[ctx->prof_used].second;
-        ++ctx->prof_used;
+    hipEvent_t pe1;
+    {
+        int prc = prof_begin(ctx, 0, arena.fixed != nullptr, &pe1);
+        if (prc) return prc;
     }
     RM_HIP(ctx, launch_raster(ctx->stream, bd, a, mode));
     if (pe1) RM_HIP(ctx, hipEventRecord(pe1, ctx->stream));
@@ -525,7 +541,11 @@ int rm_ctx_destroy(rm_ctx* ctx) {
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
         if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
-        for (auto& e : ctx->prof_events) {
+        for (auto& e : ctx->prof_events[0]) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        for (auto& e : ctx->prof_events[1]) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
@@ -595,20 +615,30 @@ int rm_profile(rm_ctx* ctx, int32_t enable) {
     return RM_OK;
 }
 
-int rm_profile_read(rm_ctx* ctx, int64_t* n_launches, double* total_ms) {
+namespace {
+int profile_read(rm_ctx* ctx, int k, int64_t* n_launches, double* total_ms) {
     if (!ctx || !n_launches || !total_ms) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
     DeviceGuard g(ctx->device);
     RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     double tot = 0.0;
-    for (size_t k = 0; k < ctx->prof_used; ++k) {
+    for (size_t i = 0; i < ctx->prof_used[k]; ++i) {
         float ms = 0.0f;
-        RM_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_events[k].first, ctx->prof_events[k].second));
+        RM_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_events[k][i].first, ctx->prof_events[k][i].second));
         tot += ms;
     }
-    *n_launches = (int64_t)ctx->prof_used;
+    *n_launches = (int64_t)ctx->prof_used[k];
     *total_ms = tot;
-    ctx->prof_used = 0;
+    ctx->prof_used[k] = 0;
     return RM_OK;
+}
+}  // namespace
+
+int rm_profile_read(rm_ctx* ctx, int64_t* n_launches, double* total_ms) {
+    return profile_read(ctx, 0, n_launches, total_ms);
+}
+
+int rm_profile_read_binning(rm_ctx* ctx, int64_t* n_launches, double* total_ms) {
+    return profile_read(ctx, 1, n_launches, total_ms);
 }
 
 int rm_graph_begin(rm_ctx* ctx) {

@@ -233,11 +233,13 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
     for (int r = r0; r <= r1; ++r) {
         double lo = (double)bx0, hi = (double)bx1;
         bool empty = false;
+        // selects instead of branches: the three edges' cases differ per lane
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            if (dy[k] < 0) lo = fmax(lo, xc[k]);
-            else if (dy[k] > 0) hi = fmin(hi, xc[k]);
-            else empty |= E[k] < 0;                 // horizontal edge: the whole row is in or out
+            const double c = xc[k];
+            lo = ((dy[k] < 0) & (c > lo)) ? c : lo;
+            hi = ((dy[k] > 0) & (c < hi)) ? c : hi;
+            empty |= (dy[k] == 0) & (E[k] < 0);     // horizontal edge: the whole row is in or out
         }
         // lo >= bx0 and hi <= bx1 already; clamp the other side before converting
         const int xa = max(bx0, (int)ceil(fmin(lo, (double)bx1 + 1.0) - 1e-6));

@@ -32,7 +32,7 @@ ABI_SYMBOLS = [
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
     "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract", "rm_depth_downsample",
     "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad", "rm_table_cost_weighted", "rm_set_bin_cap",
-    "rm_align_cost_grad_noalloc",
+    "rm_align_cost_grad_noalloc", "rm_profile_read_binning",
 ]
 TABLE_WEIGHTS = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)   # Table I as printed: reproduces E_TABLE
 
@@ -88,6 +88,7 @@ def load_library(path: Path | str | None = None):
             "rm_get_tile": [V, I32, I32, I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)],
             "rm_profile": [V, I32],
             "rm_profile_read": [V, ctypes.POINTER(I64), ctypes.POINTER(D)],
+            "rm_profile_read_binning": [V, ctypes.POINTER(I64), ctypes.POINTER(D)],
             "rm_graph_begin": [V],
             "rm_graph_end": [V, ctypes.POINTER(V)],
             "rm_graph_launch": [V, V],
@@ -174,6 +175,13 @@ class Context:
         self.lib.rm_ctx_set_stream(self.handle, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(self.lib.rm_profile_read(self.handle, ctypes.byref(n), ctypes.byref(ms)), self.handle)
+        return n.value, ms.value
+
+    def profile_read_binning(self):
+        """(number of timed binning launches, summed milliseconds); clears."""
+        self.lib.rm_ctx_set_stream(self.handle, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(self.lib.rm_profile_read_binning(self.handle, ctypes.byref(n), ctypes.byref(ms)), self.handle)
         return n.value, ms.value
 
     def get_tile(self, width, height, n_poses, n_tris):
