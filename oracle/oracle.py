@@ -584,3 +584,48 @@ def table_cost_weighted(terms, weights, mask=None):
     """sum over pixels of the weight of the pixel's Table I cell."""
     m = np.ones(terms["cell"].shape, bool) if mask is None else np.asarray(mask, bool)
     return float(np.asarray(weights, np.float64)[terms["cell"][m]].sum())
+
+
+# --------------------------------------------------------------------------
+# Color term.  Sec. IV names color as information a render-based cost takes
+# in easily, and Sec. IV-C proposes costs and rewards from the colors of
+# corresponding pixels; neither gives a form.  Reading: a pixel corresponds
+# when Table I rewards it as FO/FO (both see an occupied surface, depths
+# within eps); the map's color there is the intensity of the triangle the
+# pixel sees (flat over the triangle, as a per-face colored render shows it);
+# a corresponding pixel with both intensities finite is rewarded (-1) when
+# they differ by at most tol and penalized (+1) otherwise, like Table I's
+# cells.  The difference and the comparison are float32 operations on the
+# float32 inputs, as the rasterizer takes them.
+# --------------------------------------------------------------------------
+
+COLOR_NONE, COLOR_REWARD, COLOR_PENALTY = -1, 0, 1
+
+
+def color_cells(terms, rend, tri_color, scan_color, tol):
+    """Per-pixel color cell: COLOR_REWARD, COLOR_PENALTY or COLOR_NONE."""
+    pix = rend["pixels"]
+    ids = rend["id"]
+    hit = ids >= 0
+    c_m = np.where(hit, np.asarray(tri_color, np.float32)[np.maximum(ids, 0)], np.float32(np.nan))
+    c_s = np.asarray(scan_color, np.float32).reshape(-1)[pix]
+    out = np.full(pix.shape, COLOR_NONE, np.int64)
+    with np.errstate(invalid="ignore"):
+        diff = np.abs(c_m.astype(np.float32) - c_s)                  # float32 subtraction
+        corr = (terms["cell"] == 0) & np.isfinite(c_m) & np.isfinite(c_s)
+        out[corr] = np.where(diff[corr] <= np.float32(tol), COLOR_REWARD, COLOR_PENALTY)
+    return out
+
+
+def color_counts(cells, mask=None):
+    """(rewarded, penalized) corresponding pixels."""
+    m = np.ones(cells.shape, bool) if mask is None else np.asarray(mask, bool)
+    return int((cells[m] == COLOR_REWARD).sum()), int((cells[m] == COLOR_PENALTY).sum())
+
+
+def table_color_cost_weighted(terms, cells, weights, mask=None):
+    """Reweighted Table I plus the color cells: weights[0:9] per Table I cell,
+    weights[9] per rewarded and weights[10] per penalized corresponding pixel."""
+    w = np.asarray(weights, np.float64)
+    nr, npen = color_counts(cells, mask)
+    return table_cost_weighted(terms, w[:9], mask) + w[9] * nr + w[10] * npen

@@ -264,6 +264,45 @@ def range_image(scene: Scene, cam: Camera, T: np.ndarray, seed: int, noise_rel=0
 
 
 # --------------------------------------------------------------------------
+# surface intensity (inputs of the color term): a smooth procedural albedo,
+# intensity images of the scene and per-triangle intensities of a mesh
+# --------------------------------------------------------------------------
+
+def albedo(points) -> np.ndarray:
+    """Intensity in [0.05, 0.95] of world points: 0.5 plus 0.15 times the sum
+    of three sinusoids along the world axes (wavelengths 0.7, 0.9, 0.8 m),
+    so that every axis-aligned surface shows a pattern."""
+    p = np.asarray(points, np.float64)
+    return 0.5 + 0.15 * (np.sin(2 * np.pi * p[..., 0] / 0.7) + np.sin(2 * np.pi * p[..., 1] / 0.9)
+                         + np.sin(2 * np.pi * p[..., 2] / 0.8))
+
+
+def intensity_image(scene: Scene, cam: Camera, T: np.ndarray, seed: int, noise=0.01, z_max=8.0) -> np.ndarray:
+    """Intensity a co-registered camera reports: the albedo of the first
+    surface each pixel sees plus N(0, noise); NaN where the ray leaves the
+    room or its hit lies beyond ``z_max``.  Float32 [H, W]."""
+    rng = np.random.default_rng(seed)
+    rw, o = _rays(cam, T)
+    z = analytic_depth(scene, cam, T, z_cut=z_max)
+    ok = np.isfinite(z) & (z <= z_max)
+    p = o + rw * np.where(ok, z, 0.0)[..., None]
+    val = albedo(p) + noise * rng.standard_normal(z.shape)
+    return np.where(ok, val, np.nan).astype(np.float32)
+
+
+def triangle_albedo(xyz, tri) -> np.ndarray:
+    """Albedo at each triangle's centroid, float32 [T] (NaN for triangles
+    with a non-finite vertex)."""
+    xyz = np.asarray(xyz, np.float64)
+    tri = np.asarray(tri, np.int64)
+    if len(tri) == 0:
+        return np.zeros(0, np.float32)
+    with np.errstate(invalid="ignore"):
+        c = xyz[tri].mean(axis=1)
+        return albedo(c).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
 # procedural triangulation of the analytic scene (map meshes of the tiny and
 # corridor workloads, and closed-form test geometry)
 # --------------------------------------------------------------------------
