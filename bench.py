@@ -316,6 +316,88 @@ def trajectory_c5(rm, torch, dev, n_scans=500):
             "paper_context": "the paper aligns scans one second apart at about 2 Hz on a GTX 765M"}
 
 
+def color_term(rm, torch, dev, w, mesh, scan, T0, steps=20):
+    """The color term (Sec. IV, IV-C).
+      * throughput: the benchmarked step (64 poses, cost + gradient + LM
+        update) on the 1M-triangle map with and without colors (triangle
+        albedo at the centroids, the scan's intensity image);
+      * textured wall: the paper's derivative-free optimizer (speculative
+        batches within each alignment) from 8 starts N(0, 4 cm) / N(0, 1.5
+        deg) per axis, on E(X) alone and on E(X) + color counts (weights -1 /
+        +1, tol 0.02), with the final errors per direction of the camera
+        frame: depth alone fixes none of the in-plane motion."""
+    from paper_1702_06813_amd import align as A
+    from workloads import configs, scenes as S
+    xyz = mesh.xyz.cpu().numpy(); tri = mesh.tri.cpu().numpy()
+    cmesh = rm.Mesh(mesh.xyz, mesh.tri, mesh.cls, mesh.clusters,
+                    torch.from_numpy(S.triangle_albedo(xyz, tri)).to(dev))
+    cscan = rm.Scan(scan.depth, scan.cls, scan.cam,
+                    color=torch.from_numpy(S.intensity_image(w.scene, w.cam, w.T_true, 91, noise=0.02)).to(dev))
+    B = T0.shape[0]
+    out = torch.empty((B, rm.OUT_STRIDE), dtype=torch.float64, device=dev)
+    res = {}
+    for key, m_, s_ in (("without_color", mesh, scan), ("with_color", cmesh, cscan)):
+        T = T0.clone()
+        for _ in range(3):
+            rm.align_cost_grad(m_, s_, T, 0.1, out=out, color_tol=0.05)
+            rm.gn_step(out, T, 1e-3)
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            rm.align_cost_grad(m_, s_, T, 0.1, out=out, color_tol=0.05)
+            rm.gn_step(out, T, 1e-3)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / steps
+        res[key] = {"ms_per_step": dt * 1e3, "pose_evals_per_s": B / dt}
+    o = out.cpu().numpy()
+    res["with_color"]["corresponding_px_per_pose"] = float(
+        (o[:, rm.OUT_COLOR_REWARD] + o[:, rm.OUT_COLOR_PENALTY]).mean())
+    res["overhead"] = res["with_color"]["ms_per_step"] / res["without_color"]["ms_per_step"] - 1.0
+    log(f"color: step {res['without_color']['ms_per_step']:.3f} ms without, "
+        f"{res['with_color']['ms_per_step']:.3f} ms with colors")
+
+    wl = configs.textured_wall()
+    wm = rm.Mesh.from_arrays(*wl.map_mesh, device=dev)
+    wm.color = torch.from_numpy(wl.map_color).to(dev)
+    wm.prepare()
+    ws = rm.scan_image(torch.from_numpy(wl.scan_depth).to(dev), wl.z_min, wl.z_max, cam=wl.cam)
+    ws.color = torch.from_numpy(wl.scan_color).to(dev)
+    wts = list(rm.TABLE_WEIGHTS) + [-1.0, 1.0]
+    tol = 0.02
+    Rt = wl.T_true[:, :3]
+
+    def directions(Tp):
+        # camera-frame error components: in-plane (x, y) and along the axis,
+        # rotation about the axis (roll) and across it (pan / tilt)
+        d = Rt.T @ (Tp[:, 3] - wl.T_true[:, 3])
+        Rr = Rt.T @ Tp[:, :3]
+        rv = np.array([Rr[2, 1] - Rr[1, 2], Rr[0, 2] - Rr[2, 0], Rr[1, 0] - Rr[0, 1]]) / 2
+        return np.hypot(d[0], d[1]), abs(d[2]), np.degrees(abs(rv[2])), np.degrees(np.hypot(rv[0], rv[1]))
+
+    def summary(poses):
+        e = np.array([directions(Tp) for Tp in poses])
+        return {"in_plane_m_median": float(np.median(e[:, 0])), "depth_m_median": float(np.median(e[:, 1])),
+                "roll_deg_median": float(np.median(e[:, 2])), "tilt_deg_median": float(np.median(e[:, 3]))}
+
+    A.plain_align_batched(wm, ws, wl.poses[0], budget=50, weights=wts, color_tol=tol)     # warm-up
+    wall = {"initial": summary(wl.poses)}
+    for key, weights in (("depth_only", None), ("depth_and_color", wts)):
+        t1 = time.perf_counter()
+        runs = [A.plain_align_batched(wm, ws, Tp, weights=weights, color_tol=tol) for Tp in wl.poses]
+        dt = time.perf_counter() - t1
+        wall[key] = summary([r[0] for r in runs])
+        wall[key].update({"scans_per_s": len(runs) / dt, "launches_mean": float(np.mean([r[3] for r in runs])),
+                          "evaluations_mean": float(np.mean([r[2] for r in runs]))})
+        log(f"color wall {key}: in-plane {wall[key]['in_plane_m_median'] * 100:.2f} cm, depth "
+            f"{wall[key]['depth_m_median'] * 100:.2f} cm, roll {wall[key]['roll_deg_median']:.3f} deg, tilt "
+            f"{wall[key]['tilt_deg_median']:.3f} deg; {len(runs) / dt:.1f} scans/s")
+    wall.update({"starts": len(wl.poses), "color_tol": tol, "color_weights": [-1.0, 1.0], "eps": 0.1,
+                 "n_tris": int(wm.n_tris), "image": [wl.cam.width, wl.cam.height]})
+    res["textured_wall"] = wall
+    return res
+
+
 def icp_odometry(rm, torch, dev, n_frames=33, iters=10, reps=3):
     """Sequential depth-image alignment (Sec. V-B) on a 33-frame Kinect-like
     sequence (32 consecutive pairs, ~3.5 cm / 1.5 deg apart, 320x240 after
@@ -381,6 +463,7 @@ def main():
     ap.add_argument("--no-icp", action="store_true", help="skip the render-accelerated ICP odometry (Sec. V)")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
     ap.add_argument("--no-trajectory", action="store_true", help="skip the 500-scan trajectory alignment")
+    ap.add_argument("--no-color", action="store_true", help="skip the color term's throughput and wall alignment")
     ap.add_argument("--atomic-peaks", action="store_true",
                     help="only run the atomic-throughput microbenchmarks (a small sweep of launch shapes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -519,6 +602,8 @@ def main():
         res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in ("tiny", "kinect", "wide")}
     if not args.no_trajectory:
         res["trajectory"] = trajectory_c5(rm, torch, dev)
+    if not args.no_color:
+        res["color"] = color_term(rm, torch, dev, w, mesh, scan, T0)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a pixel sample")
         res["cpu_baseline"] = cpu_baseline(w, torch)

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define RM_ABI_VERSION 1
+#define RM_ABI_VERSION 2
 
 typedef enum {
     RM_OK = 0,
@@ -82,6 +82,8 @@ typedef struct {
     int64_t n_tris;            /* 0 .. 2^31 - 1 */
     const void* clusters;      /* device, nullable: prepared buffer from rm_mesh_clusters
                                   (cluster bounds, normals); NULL recomputes it every call */
+    const float* color;        /* device [n_tris] f32, nullable: intensity of each triangle,
+                                  the map side of the color term (NaN = none) */
 } rm_mesh;
 
 #define RM_CLUSTER_TRIS 256
@@ -93,13 +95,18 @@ typedef struct {
     const uint8_t* cls;        /* device [H][W] u8 c_s (RM_FO, RM_FU or RM_NONE) */
     const uint8_t* mask;       /* device [H][W] u8, nullable: pixels with 0 are left out of every sum */
     rm_camera cam;             /* H = cam.height, W = cam.width */
+    const float* color;        /* device [H][W] f32, nullable: intensity of each pixel, the
+                                  scan side of the color term (NaN = none) */
 } rm_scan;
 
 /* Cost parameters.  eps is the inlier/outlier threshold of Table I
- * (0.1 m in the paper); flags must be 0. */
+ * (0.1 m in the paper); flags must be 0; color_tol (finite, >= 0) is the
+ * intensity difference up to which a corresponding pixel's colors agree
+ * (color term, see RM_OUT_COLOR_REWARD). */
 typedef struct {
     float eps;
     int32_t flags;
+    float color_tol;
 } rm_cost_params;
 
 /* Per-pose result record: RM_OUT_STRIDE doubles per pose.
@@ -120,6 +127,13 @@ typedef struct {
  *   JTJ        H = sum over active pixels of J_p^T J_p, upper triangle
  *              row-major (21 values)
  *   N_VISIBLE  triangles in clusters that survived frustum culling
+ *   COLOR_REWARD, COLOR_PENALTY  the color term (Sec. IV: color can enter a
+ *              render-based cost; Sec. IV-C: costs and rewards from the colors
+ *              of corresponding pixels): over pixels in the FO/FO reward cell
+ *              of Table I whose scan color and whose triangle's color (flat
+ *              over the triangle) are both finite, the number with
+ *              |c_map - c_scan| <= color_tol (float32) and the number above
+ *              it; zero unless mesh->color and the scan's color are given
  * GRAD/JTR/JTJ/N_ACTIVE are written by rm_align_cost_grad only (zero from
  * rm_align_cost).  J_p = [m ; P_s x m] is the derivative of e_p under
  * T_wc exp(delta) with the winning triangle held fixed: n is that triangle's
@@ -134,6 +148,8 @@ enum {
     RM_OUT_JTR = 18,
     RM_OUT_JTJ = 24,
     RM_OUT_N_VISIBLE = 45,
+    RM_OUT_COLOR_REWARD = 46,
+    RM_OUT_COLOR_PENALTY = 47,
     RM_OUT_STRIDE = 48
 };
 
@@ -339,7 +355,7 @@ int rm_align_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, i
  * 64x32).  When the tile bins do not fit beside the rest, their capacity is
  * lowered and overflowing tiles are rasterized from every visible cluster of
  * their pose (slower, same records).  A call whose scratch without bins
- * exceeds the array (about 12 bytes per (pose, cluster) plus 160 bytes per
+ * exceeds the array (about 12 bytes per (pose, cluster) plus 176 bytes per
  * (pose, tile), plus 12 bytes per triangle without prepared clusters) returns
  * RM_ERR_CAPACITY and launches nothing.  All such calls on one device share
  * that device's array: calls that overlap in time on one device (different
@@ -349,14 +365,16 @@ int rm_align_cost_grad_noalloc(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* 
                                const int32_t* pose_off, const double* T_wc, rm_cost_params params, double* out);
 
 /* Table I with reweighted cells (Sec. IV-C suggests adjusting the weights of
- * the penalties and rewards of the classifications): for each of P result
- * records of rm_align_cost / rm_align_cost_grad,
- *   cost_out[p] = sum_k weights[k] * COUNTS_k(p),
- * over the nine cells in the order of RM_OUT_COUNTS.  The weights
- * (-1, +1, -1, +1, -1, +1, 0, 0, 0) give E_TABLE.
+ * the penalties and rewards of the classifications), plus the color term:
+ * for each of P result records of rm_align_cost / rm_align_cost_grad,
+ *   cost_out[p] = sum_{k<9} weights[k] * COUNTS_k(p)
+ *               + weights[9] * COLOR_REWARD(p) + weights[10] * COLOR_PENALTY(p),
+ * the nine cells in the order of RM_OUT_COUNTS.  The weights
+ * (-1, +1, -1, +1, -1, +1, 0, 0, 0, 0, 0) give E_TABLE.
  *   out       device [P][RM_OUT_STRIDE] f64
- *   weights   host, 9 doubles (finite)
+ *   weights   host, RM_N_WEIGHTS doubles (finite)
  *   cost_out  device [P] f64 */
+#define RM_N_WEIGHTS 11
 int rm_table_cost_weighted(rm_ctx* ctx, const double* out, int32_t n_poses, const double* weights, double* cost_out);
 
 /* ---------------------------------------------------------------- render-accelerated ICP (Sec. V) */

@@ -463,7 +463,7 @@ def hybrid_minimize(f, n=6, budget=700, **kw):
     return _drive(_hybrid(n, budget, **kw), f)
 
 
-def plain_align_batched(mesh, scan, T0, eps=0.1, budget=700, weights=None):
+def plain_align_batched(mesh, scan, T0, eps=0.1, budget=700, weights=None, color_tol=0.0):
     """The paper's optimizer for one alignment with its independent points
     evaluated together: every batch of the speculative hybrid optimizer (the
     finite-difference stencil, the line-search steps, the initial simplex,
@@ -476,7 +476,7 @@ def plain_align_batched(mesh, scan, T0, eps=0.1, budget=700, weights=None):
     def f(xs):
         X = torch.from_numpy(np.stack(xs)).to(dev)
         Td = R.se3_retract(T0d.expand(len(xs), 12).contiguous(), X)
-        out = R.align_cost(mesh, scan, Td, eps)
+        out = R.align_cost(mesh, scan, Td, eps, color_tol=color_tol)
         v = out[:, R.OUT_E_TABLE] if weights is None else R.table_cost_weighted(out, weights)
         return v.cpu().numpy()
 
@@ -485,11 +485,13 @@ def plain_align_batched(mesh, scan, T0, eps=0.1, budget=700, weights=None):
     return R.se3_retract(T0d, xd).cpu().numpy().reshape(3, 4), fx, evals, launches
 
 
-def plain_align(mesh, scan, T0, eps=0.1, budget=700, weights=None):
+def plain_align(mesh, scan, T0, eps=0.1, budget=700, weights=None, color_tol=0.0):
     """The paper's plain form: minimize E(X) (Table I) of one pose with the
     derivative-free hybrid optimizer, one single-pose render per evaluation.
-    weights: optional nine Table I cell weights (rm_table_cost_weighted;
-    Sec. IV-C suggests reweighting the penalties and rewards), None for E(X).
+    weights: optional nine Table I cell weights, or eleven with the color
+    reward and penalty weights (rm_table_cost_weighted; Sec. IV-C suggests
+    reweighting the penalties and rewards, and color costs and rewards),
+    None for E(X); color_tol: the color term's agreement threshold.
     T0: [12] or [3,4] (host).  Returns (T [3,4] numpy, E, evaluations)."""
     dev = mesh.xyz.device
     T0d = torch.as_tensor(np.asarray(T0, np.float64).reshape(1, 12), device=dev)
@@ -500,7 +502,7 @@ def plain_align(mesh, scan, T0, eps=0.1, budget=700, weights=None):
     def f(x):
         xd.copy_(torch.from_numpy(np.asarray(x, np.float64).reshape(1, 6)))
         R.se3_retract(T0d, xd, out=Td)
-        R.align_cost(mesh, scan, Td, eps, out=out)
+        R.align_cost(mesh, scan, Td, eps, out=out, color_tol=color_tol)
         if weights is not None:
             return float(R.table_cost_weighted(out, weights)[0].item())
         return float(out[0, R.OUT_E_TABLE].item())
@@ -531,7 +533,8 @@ def lockstep(gens, evaluate):
                 result[k] = stop.value
 
 
-def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weights=None, speculative=False):
+def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weights=None, speculative=False,
+                        color_tol=0.0):
     """The paper's optimizer for many alignments at once: every instance runs
     the same hybrid optimizer as plain_align, and each round evaluates the
     next point of every unfinished instance in one launch (T0: [K,3,4] or
@@ -557,7 +560,7 @@ def batched_plain_align(mesh, scans, T0, eps=0.1, budget=700, scan_of=None, weig
         counts = [int((scan_of[kk] == sc).sum()) for sc in used]
         X = torch.from_numpy(np.stack([xs[j] for j in order])).to(dev)
         Td = R.se3_retract(T0d[kk].contiguous(), X)
-        out = R.align_cost(mesh, [scans[sc] for sc in used], Td, eps, poses_per_scan=counts)
+        out = R.align_cost(mesh, [scans[sc] for sc in used], Td, eps, poses_per_scan=counts, color_tol=color_tol)
         v = (out[:, R.OUT_E_TABLE] if weights is None else R.table_cost_weighted(out, weights)).cpu().numpy()
         res = np.empty(len(ks))
         res[order] = v

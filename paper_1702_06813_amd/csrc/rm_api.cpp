@@ -342,6 +342,8 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.rec = reinterpret_cast<float*>(at(o_rec));
         a.eps = eps;
         a.vnrm = vnrm;
+        a.tri_color = mode == kCost || mode == kGrad ? mesh->color : nullptr;
+        a.color_tol = bd.color_tol;
         a.depth_out = depth_out;
         a.tri_out = tri_out;
         a.cls_out = cls_out;
@@ -474,10 +476,13 @@ int rm::align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int
     if (!(params.eps > 0.0f) || !std::isfinite(params.eps))
         return fail(ctx, RM_ERR_INVALID_ARG, "eps must be positive and finite");
     if (params.flags != 0) return fail(ctx, RM_ERR_INVALID_ARG, "flags must be 0");
+    if (!(params.color_tol >= 0.0f) || !std::isfinite(params.color_tol))
+        return fail(ctx, RM_ERR_INVALID_ARG, "color_tol must be finite and >= 0");
     if (pose_off[0] != 0) return fail(ctx, RM_ERR_INVALID_ARG, "pose_off[0] must be 0");
     BatchDesc bd;
     std::memset(&bd, 0, sizeof(bd));
     bd.n_scans = S;
+    bd.color_tol = params.color_tol;
     for (int s = 0; s < S; ++s) {
         if (pose_off[s + 1] < pose_off[s]) return fail(ctx, RM_ERR_INVALID_ARG, "pose_off must be non-decreasing");
         if (!scans[s].depth || !scans[s].cls)
@@ -487,6 +492,7 @@ int rm::align_common(rm_ctx* ctx, const rm_mesh* mesh, const rm_scan* scans, int
         bd.s[s].depth = scans[s].depth;
         bd.s[s].cls = scans[s].cls;
         bd.s[s].mask = scans[s].mask;
+        bd.s[s].color = scans[s].color;
         bd.s[s].pose_off = pose_off[s];
         bd.s[s].n_poses = pose_off[s + 1] - pose_off[s];
     }
@@ -848,6 +854,7 @@ int rm_icp_cost_grad(rm_ctx* ctx, const rm_mesh* mesh, const float* vertex_norma
     rm_cost_params p;
     p.eps = tol;
     p.flags = 0;
+    p.color_tol = 0.0f;
     return align_common(ctx, mesh, scans, n_scans, pose_off, T_wc, p, out, kIcp, vertex_normals, nullptr);
 }
 
@@ -869,7 +876,7 @@ int rm_table_cost_weighted(rm_ctx* ctx, const double* out, int32_t n_poses, cons
     if (n_poses < 0) return fail(ctx, RM_ERR_INVALID_ARG, "n_poses < 0");
     if (n_poses == 0) return RM_OK;
     if (!out || !weights || !cost_out) return fail(ctx, RM_ERR_INVALID_ARG, "NULL argument");
-    for (int k = 0; k < 9; ++k)
+    for (int k = 0; k < RM_N_WEIGHTS; ++k)
         if (!std::isfinite(weights[k])) return fail(ctx, RM_ERR_INVALID_ARG, "weights must be finite");
     DeviceGuard g(ctx->device);
     RM_HIP(ctx, launch_weighted(ctx->stream, out, n_poses, weights, cost_out));

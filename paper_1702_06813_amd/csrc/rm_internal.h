@@ -11,7 +11,7 @@ namespace rm {
 constexpr int kWG = 256;                 // threads per workgroup everywhere
 constexpr int kClusterTris = RM_CLUSTER_TRIS;
 constexpr int kQuadBlock = 8;            // meshify emits 8x8 blocks of quads
-constexpr int kRecFields = 40;           // per-(pose, tile) partial record, 4-byte fields
+constexpr int kRecFields = 41;           // per-(pose, tile) partial record, 4-byte fields
 constexpr int kSnapLimit = 1 << 29;      // |snapped coordinate| must stay below this
 constexpr int kBinTable = 2048;          // tiles of a cluster rectangle binned per LDS pass (taller
                                          // rectangles are binned in bands of rows)
@@ -31,6 +31,7 @@ struct ScanDesc {
     const float* depth;
     const uint8_t* cls;
     const uint8_t* mask;
+    const float* color;   // scan intensity (color term), nullable
     float fx, fy, cx, cy;
     int32_t width, height;
     float z_near, z_far;
@@ -44,6 +45,7 @@ struct BatchDesc {
     int32_t n_scans;
     int32_t n_poses;
     int32_t tile_w, tile_h;
+    float color_tol;      // color term: agreement threshold of corresponding pixels
     int64_t n_items;
     ScanDesc s[RM_MAX_SCANS];
 };
@@ -74,6 +76,8 @@ struct RasterArgs {
     float* rec;                  // partial records [n_records][kRecFields]
     float eps;                   // Table I threshold; the association tolerance in ICP mode
     const float* vnrm;           // ICP mode: [n_vertices][3] world-frame vertex normals
+    const float* tri_color;      // cost and gradient modes, nullable: [T] triangle intensities
+    float color_tol;
     // render outputs
     float* depth_out;
     int32_t* tri_out;

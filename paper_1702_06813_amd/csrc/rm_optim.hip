@@ -153,16 +153,19 @@ hipError_t launch_retract(hipStream_t st, const double* T_in, const double* delt
 
 namespace {
 
-struct CellW { double w[9]; };
+struct CellW { double w[RM_N_WEIGHTS]; };
 
-// Weighted Table I cost of each pose from its nine cell counts.
+// Weighted Table I cost of each pose from its nine cell counts and its two
+// color counts.
 __global__ void k_weighted(const double* __restrict__ out, int32_t P, CellW cw, double* __restrict__ cost) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const double* c = out + (int64_t)p * RM_OUT_STRIDE + RM_OUT_COUNTS;
+    const double* o = out + (int64_t)p * RM_OUT_STRIDE;
     double e = 0.0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) e += cw.w[k] * c[k];
+    for (int k = 0; k < 9; ++k) e += cw.w[k] * o[RM_OUT_COUNTS + k];
+    e += cw.w[9] * o[RM_OUT_COLOR_REWARD];
+    e += cw.w[10] * o[RM_OUT_COLOR_PENALTY];
     cost[p] = e;
 }
 
@@ -170,7 +173,7 @@ __global__ void k_weighted(const double* __restrict__ out, int32_t P, CellW cw, 
 
 hipError_t launch_weighted(hipStream_t st, const double* out, int32_t P, const double* w, double* cost) {
     CellW cw;
-    for (int k = 0; k < 9; ++k) cw.w[k] = w[k];
+    for (int k = 0; k < RM_N_WEIGHTS; ++k) cw.w[k] = w[k];
     hipLaunchKernelGGL(k_weighted, dim3((unsigned)((P + kWG - 1) / kWG)), dim3(kWG), 0, st, out, P, cw, cost);
     return hipGetLastError();
 }

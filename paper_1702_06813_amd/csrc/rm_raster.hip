@@ -758,6 +758,7 @@ struct Acc {
     float jtr[6];
     float jtj[21];
     float sse;             // ICP mode: sum of squared point-to-plane residuals
+    int col[2];            // color term: rewarded, penalized corresponding pixels
 };
 
 // Table I cell of a pixel and its value: returns the cell (0..8) and sets s.
@@ -912,6 +913,10 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     // ---------------------------------------------------------------- resolve
     Acc acc;
     acc.e_table = 0; acc.n_active = 0; acc.e_soft = 0.0f; acc.sse = 0.0f;
+    acc.col[0] = 0; acc.col[1] = 0;
+    // color term: both sides' intensities given (cost and gradient modes)
+    const float* scol = MODE == kCost || MODE == kGrad ? sd.color : nullptr;
+    const bool color = a.tri_color != nullptr && scol != nullptr;
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc.cnt[k] = 0;
 #pragma unroll
@@ -991,6 +996,16 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         acc.e_table += s;
 #pragma unroll
         for (int k = 0; k < 9; ++k) acc.cnt[k] += cell == k;
+        if (color && cell == 0) {
+            // corresponding pixel: the triangle's and the scan's intensities
+            // agree within color_tol (float32 difference, both finite)
+            const float cm = a.tri_color[id], cs = scol[pix];
+            if (isfinite(cm) && isfinite(cs)) {
+                const bool agree = fabsf(cm - cs) <= a.color_tol;
+                acc.col[0] += agree;
+                acc.col[1] += !agree;
+            }
+        }
         if (cell >= 6) continue;
         // Camera-frame unit normal n of the winning triangle and g = |n . ray|:
         // e = dz g is the scan point's signed distance from that triangle's plane.
@@ -1046,6 +1061,15 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         for (int k = 0; k < 21; ++k) v[18 + k] = acc.jtj[k];
     }
     if (MODE == kIcp) v[39] = acc.sse;
+    int col0 = 0, col1 = 0;
+    if (MODE != kIcp && color) {
+        col0 = acc.col[0]; col1 = acc.col[1];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            col0 += __shfl_xor(col0, off);
+            col1 += __shfl_xor(col1, off);
+        }
+    }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         if (f <= 10) {
@@ -1063,11 +1087,20 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     if (lane == 0) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) red[wave][f] = v[f];
+        if (MODE != kIcp) {
+            red[wave][39] = __int_as_float(col0);
+            red[wave][40] = __int_as_float(col1);
+        }
     }
     __syncthreads();
     if (tid < kRecFields) {
         float* rec = a.rec + it.rec * kRecFields;
-        if (tid >= NF) {
+        if (MODE != kIcp && tid >= 39) {       // color counts (integers)
+            int x = 0;
+#pragma unroll
+            for (int w = 0; w < kWG / 64; ++w) x += __float_as_int(red[w][tid]);
+            rec[tid] = __int_as_float(x);
+        } else if (tid >= NF) {
             rec[tid] = 0.0f;
         } else if (tid <= 10) {
             int x = 0;
@@ -1294,7 +1327,7 @@ __global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd,
     const int ntile = sd.tiles_x * sd.tiles_y;
     const float* r = rec + (sd.rec_off + (int64_t)(pose - sd.pose_off) * ntile) * kRecFields;
     const int f = threadIdx.x % kRecFields, j = threadIdx.x / kRecFields;
-    if (f <= 10) {
+    if (f <= 10 || (mode != kIcp && f >= 39)) {      // integer fields (counts)
         int64_t acc = 0;
         for (int t = j; t < ntile; t += kRedSplit) acc += __float_as_int(r[(int64_t)t * kRecFields + f]);
         part[j][f] = (double)acc;
@@ -1337,6 +1370,8 @@ __global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd,
         else if (g >= RM_OUT_JTR && g < RM_OUT_JTR + 6) x = grad ? val[12 + g - RM_OUT_JTR] : 0.0;
         else if (g >= RM_OUT_JTJ && g < RM_OUT_JTJ + 21) x = grad ? val[18 + g - RM_OUT_JTJ] : 0.0;
         else if (g == RM_OUT_N_VISIBLE) x = (double)vis_tris[pose];
+        else if (g == RM_OUT_COLOR_REWARD) x = val[39];
+        else if (g == RM_OUT_COLOR_PENALTY) x = val[40];
         o[g] = x;
     }
 }

@@ -21,6 +21,7 @@ RM_OK, RM_ERR_INVALID_ARG, RM_ERR_OOM, RM_ERR_DEVICE, RM_ERR_CAPACITY, RM_ERR_UN
 FO, FU, UO, NONE = 0, 1, 2, 3
 OUT_E_TABLE, OUT_E_SOFT, OUT_COUNTS, OUT_N_ACTIVE = 0, 1, 2, 11
 OUT_GRAD, OUT_JTR, OUT_JTJ, OUT_N_VISIBLE, OUT_STRIDE = 12, 18, 24, 45, 48
+OUT_COLOR_REWARD, OUT_COLOR_PENALTY = 46, 47
 OUT_ICP_COST, OUT_ICP_SSE, OUT_ICP_N_SCAN, OUT_ICP_N_MODEL = 0, 1, 2, 3
 MAX_NORMAL_RADIUS = 8
 MAX_SCANS = 32
@@ -35,6 +36,7 @@ ABI_SYMBOLS = [
     "rm_align_cost_grad_noalloc", "rm_profile_read_binning",
 ]
 TABLE_WEIGHTS = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)   # Table I as printed: reproduces E_TABLE
+N_WEIGHTS = 11            # nine Table I cells, then the color reward and penalty
 
 
 class RenderMapError(RuntimeError):
@@ -51,15 +53,17 @@ class CCamera(ctypes.Structure):
 
 class CMesh(ctypes.Structure):
     _fields_ = [("xyz", ctypes.c_void_p), ("n_vertices", ctypes.c_int64), ("tri", ctypes.c_void_p),
-                ("cls", ctypes.c_void_p), ("n_tris", ctypes.c_int64), ("clusters", ctypes.c_void_p)]
+                ("cls", ctypes.c_void_p), ("n_tris", ctypes.c_int64), ("clusters", ctypes.c_void_p),
+                ("color", ctypes.c_void_p)]
 
 
 class CScan(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_void_p), ("cls", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("cam", CCamera)]
+    _fields_ = [("depth", ctypes.c_void_p), ("cls", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("cam", CCamera),
+                ("color", ctypes.c_void_p)]
 
 
 class CCostParams(ctypes.Structure):
-    _fields_ = [("eps", ctypes.c_float), ("flags", ctypes.c_int32)]
+    _fields_ = [("eps", ctypes.c_float), ("flags", ctypes.c_int32), ("color_tol", ctypes.c_float)]
 
 
 _lib = None
@@ -239,6 +243,7 @@ class Mesh:
     tri: torch.Tensor          # [T,3] i32
     cls: torch.Tensor          # [T] u8
     clusters: torch.Tensor | None = None
+    color: torch.Tensor | None = None     # [T] f32 triangle intensities (color term)
 
     @property
     def n_tris(self):
@@ -253,8 +258,13 @@ class Mesh:
             raise ValueError("xyz must be [V,3] and tri [T,3]")
         if self.cls.shape[0] != self.tri.shape[0]:
             raise ValueError("cls must have one entry per triangle")
+        if self.color is not None:
+            _need(self.color, torch.float32, "color", dev)
+            if tuple(self.color.shape) != (self.tri.shape[0],):
+                raise ValueError("color must have one entry per triangle")
         return CMesh(self.xyz.data_ptr(), self.xyz.shape[0], self.tri.data_ptr(), self.cls.data_ptr(),
-                     self.tri.shape[0], self.clusters.data_ptr() if self.clusters is not None else None)
+                     self.tri.shape[0], self.clusters.data_ptr() if self.clusters is not None else None,
+                     self.color.data_ptr() if self.color is not None else None)
 
     def prepare(self):
         """Computes the cluster bounds once (rm_mesh_clusters)."""
@@ -262,7 +272,7 @@ class Mesh:
         n = int(load_library().rm_mesh_clusters_size(self.n_tris))
         self.clusters = torch.empty(max(n, 1), dtype=torch.uint8, device=self.xyz.device)
         m = CMesh(self.xyz.data_ptr(), self.xyz.shape[0], self.tri.data_ptr(), self.cls.data_ptr(),
-                  self.tri.shape[0], None)
+                  self.tri.shape[0], None, None)
         ctx.call("rm_mesh_clusters", ctypes.byref(m), _ptr(self.clusters))
         return self
 
@@ -278,7 +288,11 @@ class Mesh:
         xyz, tri, cls, off = [], [], [], 0
         for m in meshes:
             xyz.append(m.xyz); tri.append(m.tri + off); cls.append(m.cls); off += m.xyz.shape[0]
-        return Mesh(torch.cat(xyz).contiguous(), torch.cat(tri).contiguous(), torch.cat(cls).contiguous())
+        color = None
+        if all(m.color is not None for m in meshes):
+            color = torch.cat([m.color for m in meshes]).contiguous()
+        return Mesh(torch.cat(xyz).contiguous(), torch.cat(tri).contiguous(), torch.cat(cls).contiguous(),
+                    color=color)
 
 
 @dataclass
@@ -288,6 +302,7 @@ class Scan:
     cls: torch.Tensor
     cam: object
     mask: torch.Tensor | None = None
+    color: torch.Tensor | None = None     # [H,W] f32 pixel intensities (color term), NaN = none
 
     def struct(self) -> CScan:
         dev = self.depth.device
@@ -300,8 +315,13 @@ class Scan:
             _need(self.mask, torch.uint8, "mask", dev)
             if tuple(self.mask.shape) != (H, W):
                 raise ValueError("mask must match the image")
+        if self.color is not None:
+            _need(self.color, torch.float32, "scan color", dev)
+            if tuple(self.color.shape) != (H, W):
+                raise ValueError("color must match the image")
         return CScan(self.depth.data_ptr(), self.cls.data_ptr(),
-                     self.mask.data_ptr() if self.mask is not None else None, ccamera(self.cam))
+                     self.mask.data_ptr() if self.mask is not None else None, ccamera(self.cam),
+                     self.color.data_ptr() if self.color is not None else None)
 
 
 # ---------------------------------------------------------------------------- entry points
@@ -378,7 +398,7 @@ def _scan_args(scans, poses_per_scan):
     return arr, offs, off[-1]
 
 
-def _align(name, mesh, scans, poses_per_scan, T_wc, eps, out):
+def _align(name, mesh, scans, poses_per_scan, T_wc, eps, out, color_tol=0.0):
     dev = mesh.xyz.device
     if isinstance(scans, Scan):
         scans = [scans]
@@ -396,18 +416,19 @@ def _align(name, mesh, scans, poses_per_scan, T_wc, eps, out):
             raise ValueError("out must be [P, 48]")
     m = mesh.struct()
     context(dev).call(name, ctypes.byref(m), arr, len(scans), ctypes.cast(offs, ctypes.c_void_p), _ptr(T),
-                      CCostParams(eps, 0), _ptr(out))
+                      CCostParams(eps, 0, color_tol), _ptr(out))
     return out
 
 
-def align_cost(mesh, scans, T_wc, eps=0.1, poses_per_scan=None, out=None):
-    """rm_align_cost: [P, 48] result records (E_table, E_soft, counts, ...)."""
-    return _align("rm_align_cost", mesh, scans, poses_per_scan, T_wc, eps, out)
+def align_cost(mesh, scans, T_wc, eps=0.1, poses_per_scan=None, out=None, color_tol=0.0):
+    """rm_align_cost: [P, 48] result records (E_table, E_soft, counts, ...;
+    the color counts when the mesh and the scans carry colors)."""
+    return _align("rm_align_cost", mesh, scans, poses_per_scan, T_wc, eps, out, color_tol)
 
 
-def align_cost_grad(mesh, scans, T_wc, eps=0.1, poses_per_scan=None, out=None):
+def align_cost_grad(mesh, scans, T_wc, eps=0.1, poses_per_scan=None, out=None, color_tol=0.0):
     """rm_align_cost_grad: as align_cost plus gradient and Gauss-Newton blocks."""
-    return _align("rm_align_cost_grad", mesh, scans, poses_per_scan, T_wc, eps, out)
+    return _align("rm_align_cost_grad", mesh, scans, poses_per_scan, T_wc, eps, out, color_tol)
 
 
 def _records(out, P, dev):
@@ -430,13 +451,13 @@ def _per_pose(t, P, n, dtype, name, dev):
     return t
 
 
-def align_cost_grad_noalloc(mesh, scans, T_wc, out, eps=0.1, poses_per_scan=None):
+def align_cost_grad_noalloc(mesh, scans, T_wc, out, eps=0.1, poses_per_scan=None, color_tol=0.0):
     """rm_align_cost_grad_noalloc: rm_align_cost_grad with its scratch in the
     library's fixed device array (no allocation by the library); `out`
     ([P, 48] f64) must be given."""
     if out is None:
         raise ValueError("out must be given")
-    return _align("rm_align_cost_grad_noalloc", mesh, scans, poses_per_scan, T_wc, eps, out)
+    return _align("rm_align_cost_grad_noalloc", mesh, scans, poses_per_scan, T_wc, eps, out, color_tol)
 
 
 def gn_step(out: torch.Tensor, T_wc: torch.Tensor, lam: float = 0.0, delta_out=None):
@@ -614,11 +635,18 @@ def icp_cost_grad(mesh, scans, T_wc, vertex_normals: torch.Tensor, tol: float = 
 
 
 def table_cost_weighted(out: torch.Tensor, weights=TABLE_WEIGHTS) -> torch.Tensor:
-    """rm_table_cost_weighted: [P] f64 cost sum_k w_k counts_k of result records."""
+    """rm_table_cost_weighted: [P] f64 cost sum_k w_k counts_k of result
+    records: nine Table I cell weights, optionally followed by the weights of
+    the color reward and penalty counts (zero when only nine are given)."""
     import numpy as np
     dev = out.device
     _need(out, torch.float64, "out", dev)
-    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(9))
+    w = np.asarray(weights, dtype=np.float64).reshape(-1)
+    if w.size == 9:
+        w = np.concatenate([w, [0.0, 0.0]])
+    if w.size != N_WEIGHTS:
+        raise ValueError(f"weights must hold 9 or {N_WEIGHTS} values")
+    w = np.ascontiguousarray(w)
     P = out.reshape(-1, OUT_STRIDE).shape[0]
     cost = torch.empty(P, dtype=torch.float64, device=dev)
     context(dev).call("rm_table_cost_weighted", _ptr(out), P, w.ctypes.data_as(ctypes.c_void_p), _ptr(cost))

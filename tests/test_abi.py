@@ -47,7 +47,10 @@ def test_null_context_is_rejected_without_a_device(lib):
     assert lib.rm_render_depth(None, None, None, None, 0, None, None, None) == -1
     assert b"ctx" in lib.rm_last_error(None)
     assert lib.rm_gn_step(None, None, 1, ctypes.c_double(0.0), None, None) == -1
-    assert lib.rm_align_cost(None, None, None, 1, None, None, ctypes.c_int64(0), None) == -1
+    from paper_1702_06813_amd.rendermap import CCostParams
+    fn = lib.rm_align_cost
+    fn.argtypes = [ctypes.c_void_p] * 6 + [CCostParams, ctypes.c_void_p]
+    assert fn(None, None, None, 1, None, None, CCostParams(0.1, 0, 0.0), None) == -1
 
 
 def test_cluster_size_rule(lib):
@@ -104,3 +107,24 @@ def test_microbenchmark_library_exports_and_rejects_bad_arguments():
     assert mb.rm_mb_global_atomic_add(16, 8, 5, ctypes.byref(s), ctypes.byref(n)) == -1
     assert mb.rm_mb_global_atomic_add(16, 8, 25, ctypes.byref(s), ctypes.byref(n)) == -1
     assert mb.rm_mb_global_atomic_add(16, 8, 12, None, ctypes.byref(n)) == -1
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """sizeof and offsetof of the ABI structs, as a C compiler lays them out
+    from the header, equal the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    from paper_1702_06813_amd import rendermap as R
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", str(ROOT / "include"), "-o", str(exe),
+                    str(ROOT / "tests" / "native" / "abi_layout.c")], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    mirrors = {"rm_camera": R.CCamera, "rm_mesh": R.CMesh, "rm_scan": R.CScan, "rm_cost_params": R.CCostParams}
+    for name, cls in mirrors.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for key, val in got.items():
+            if key.startswith(name + "."):
+                assert getattr(cls, key.split(".", 1)[1]).offset == int(val), key

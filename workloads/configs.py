@@ -36,6 +36,8 @@ class Workload:
     stride: int = 1
     max_edge: float = 0.1
     smooth_radius: int = 0             # node smoothing window half-width of the map meshing
+    map_color: np.ndarray | None = None    # [T] f32 triangle intensities of map_mesh (color term)
+    scan_color: np.ndarray | None = None   # [H,W] f32 intensity image of the query scan
 
 
 def _room_center(scene):
@@ -111,6 +113,26 @@ def wide(seed: int = 4, n_poses: int = 256, cell=0.018) -> Workload:
     poses = np.stack([S.perturb(T, rng, 0.03, np.deg2rad(1.5)) for _ in range(n_poses)])
     return Workload("wide", cam, scene, T, depth, poses, map_mesh=mesh)
 
+
+
+def textured_wall(seed: int = 8, n_poses: int = 8, cell=0.02) -> Workload:
+    """A QVGA camera 1.5 m in front of a wall that fills its view (empty
+    4x4x2.5 m room, procedural mesh on a 2 cm grid, ~0.36M triangles) with
+    the procedural albedo on every surface: the triangles carry the albedo
+    at their centroids, the scan an intensity image with N(0, 0.01) noise.
+    Depth alone leaves the pose's in-plane translation and its rotation about
+    the wall's normal unobservable; color fixes them.  n_poses starts
+    N(0, 4 cm) / N(0, 1.5 deg) per axis around the truth."""
+    cam = S.QVGA
+    scene = S.random_box_room(seed, (4.0, 4.0, 2.5), 0)
+    mesh = S.triangulate_scene(scene, cell=cell)
+    T = S.look_pose(np.array([2.0, 2.5, 1.25]), np.pi / 2)        # facing the wall y = 4 from 1.5 m
+    depth = S.range_image(scene, cam, T, seed + 13, noise_rel=0.005)
+    color = S.intensity_image(scene, cam, T, seed + 17, noise=0.01)
+    rng = np.random.default_rng(seed)
+    poses = np.stack([S.perturb(T, rng, 0.04, np.deg2rad(1.5)) for _ in range(n_poses)])
+    return Workload("textured_wall", cam, scene, T, depth, poses, map_mesh=mesh,
+                    map_color=S.triangle_albedo(mesh[0], mesh[1]), scan_color=color)
 
 @dataclass
 class StreamScan:
