@@ -125,6 +125,7 @@ constexpr double kOccMargin = 1.0 + 1e-6;
 // The depth snapshot keeps one value per kSeg-pixel segment of each tile row
 // (index row * kSegs + x / kSeg) and the tile's farthest at kSnapTile.
 constexpr int kSeg = 16, kSegs = 4, kSnapTile = 32 * kSegs;
+constexpr int kSnapEvery = 4;            // rounds between snapshot refreshes after the first ones
 
 // Minimum of x over aligned groups of G consecutive lanes (G = 8 or 16, one
 // DPP row or half row): swaps inside quads, then the half-row and row
@@ -511,13 +512,17 @@ __device__ __forceinline__ bool footprint(const PoseF& P, const CamF& cam, float
     // float32 rotations), which moves the projection of a point of depth z
     // at most (f + |u - c|) / z times as far; bounded here with twice that,
     // the polygon's least depth, and |u - c| up to the larger image side.
+    // (the hardware reciprocal's relative error, ~2^-22, is far inside the
+    // factor 2 of the bound)
     const float zmin = fmaxf(fminf(Q0.z, fminf(Q1.z, fminf(Q2.z, Q3.z))), znp);
     const float tn = fabsf(P.tf[0]) + fabsf(P.tf[1]) + fabsf(P.tf[2]);
-    f.m = kBinMargin + 0x1p-23f * (tn + 9.0f * dm) * (fmaxf(cam.fx, cam.fy) + (float)max(cam.W, cam.H)) / zmin;
+    f.m = kBinMargin + 0x1p-23f * (tn + 9.0f * dm) * (fmaxf(cam.fx, cam.fy) + (float)max(cam.W, cam.H)) *
+                           __builtin_amdgcn_rcpf(zmin);
     proj_approx(cam, Q0, f.u[0], f.v[0]);
     proj_approx(cam, Q1, f.u[1], f.v[1]);
     proj_approx(cam, Q2, f.u[2], f.v[2]);
-    proj_approx(cam, Q3, f.u[3], f.v[3]);
+    if (nin == 3) { f.u[3] = f.u[2]; f.v[3] = f.v[2]; }       // a triangle repeats its last vertex
+    else proj_approx(cam, Q3, f.u[3], f.v[3]);
     return true;
 }
 
@@ -870,11 +875,18 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     t1 = entry(1);
     load_indices(a.tri, a.vmax, t1, I1);
     t2 = entry(2);
+    // The snapshot is refreshed after each of the first kSnapEvery rounds and
+    // then after every kSnapEvery-th: the near surfaces arrive first, and an
+    // older snapshot stays a valid bound (keys only move nearer), so later
+    // rounds cull almost as well at a fraction of the cost.  Buffer cb is
+    // read by the current round; a refresh fills the other and swaps.
     if (tid <= kSnapTile) q.rowmin[0][tid] = 0.0f;   // round 0 sees an empty buffer
+    int cb = 0;
     for (int r = 0; r < nr; ++r) {
+        const bool snap_now = r + 1 < nr && (r < kSnapEvery || r % kSnapEvery == 0);
         if (tid == 0) { q.big.n = 0; q.big.njobs = 0; }
-        if (tid == 0) q.rowmin[(r + 1) & 1][kSnapTile] = __int_as_float(0x7f800000);
-        const float* rmin = q.rowmin[r & 1];
+        if (tid == 0 && snap_now) q.rowmin[cb ^ 1][kSnapTile] = __int_as_float(0x7f800000);
+        const float* rmin = q.rowmin[cb];
         load_vertices(a.xyz, t1, I1, nxt);
         load_indices(a.tri, a.vmax, t2, I2);
         t3 = entry(r + 3);
@@ -888,9 +900,9 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         // kG lanes of a group cover one kSeg-pixel segment (or, for 8-pixel
         // tile rows, one row): a group minimum and one store per segment;
         // the tile's farthest is a wave minimum and one atomic per wave.
-        if (r + 1 < nr) {
+        if (snap_now) {
             constexpr int kG = TW < kSeg ? TW : kSeg;
-            float* snap = q.rowmin[(r + 1) & 1];
+            float* snap = q.rowmin[cb ^ 1];
             uint32_t tmin = 0x7f800000u;
             for (int p = tid; p < TW * TH; p += kWG) {
                 const uint32_t wb = group_min<kG>(~(uint32_t)(keys[p] >> 32));
@@ -904,6 +916,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
                 if (lane == 0) atomicMin((unsigned int*)&snap[kSnapTile], tmin);
             }
         }
+        if (snap_now) cb ^= 1;
         cur = nxt;
         t1 = t2;
         I1[0] = I2[0]; I1[1] = I2[1]; I1[2] = I2[2];
