@@ -184,6 +184,53 @@ def test_render_far_from_origin(rm):
             rm.context().set_tile(0, 0)
 
 
+def _layer_stack(seed, n_layers=80, nx=20, ny=16):
+    """n_layers tilted, holed rectangles stacked 1.0 .. 3.0 m in front of
+    the identity camera, each slightly wider than the 64x48 view at its
+    depth, triangle ids shuffled so that every bin mixes the layers."""
+    rng = np.random.default_rng(seed)
+    xyz, tri = [], []
+    for k in range(n_layers):
+        z = 1.0 + 2.0 * k / n_layers
+        sx, sy = rng.uniform(-0.15, 0.15, size=2)          # depth slopes: layers cross each other
+        hx, hy = 0.7 * z, 0.55 * z
+        u = np.linspace(-hx, hx, nx + 1)
+        v = np.linspace(-hy, hy, ny + 1)
+        uu, vv = np.meshgrid(u, v, indexing="ij")
+        pts = np.stack([uu, vv, z + sx * uu + sy * vv], -1).reshape(-1, 3)
+        idx = np.arange((nx + 1) * (ny + 1)).reshape(nx + 1, ny + 1)
+        keep = rng.random((nx, ny)) > 0.25                  # holes show deeper layers through
+        q00, q01 = idx[:-1, :-1][keep], idx[:-1, 1:][keep]
+        q10, q11 = idx[1:, :-1][keep], idx[1:, 1:][keep]
+        off = sum(len(p) for p in xyz)
+        tri.append(np.concatenate([np.stack([q00, q01, q11], 1), np.stack([q00, q11, q10], 1)]) + off)
+        xyz.append(pts)
+    xyz = np.concatenate(xyz).astype(np.float32)
+    tri = np.concatenate(tri).astype(np.int32)
+    tri = tri[rng.permutation(len(tri))]
+    return xyz, tri, np.zeros(len(tri), np.uint8)
+
+
+def test_render_deep_stack_many_rounds(rm):
+    """About 38,000 triangles in 80 crossing, holed layers over a 64x48 view,
+    in shuffled order: tile bins take tens of rounds, so the depth
+    snapshot's refresh schedule (every round at first, then every few) and
+    the occlusion skips it drives decide most triangles.  Full-frame parity
+    with the oracle at three tile shapes and five poses."""
+    _say("render deep stack")
+    mesh = _layer_stack(23)
+    cam = S.Camera(52.5, 52.5, 31.5, 23.5, 64, 48, z_near=0.1, z_far=16.0)
+    T = np.zeros((3, 4)); T[:, :3] = np.eye(3)
+    rng = np.random.default_rng(29)
+    poses = [T] + [S.perturb(T, rng, 0.05, np.deg2rad(3)) for _ in range(4)]
+    for tile in ((64, 32), (16, 16), (8, 8)):
+        rm.context().set_tile(*tile)
+        try:
+            _render_cmp(rm, mesh, cam, poses)
+        finally:
+            rm.context().set_tile(0, 0)
+
+
 def test_duplicate_triangles_lowest_id_wins(rm):
     """Every triangle of the tiny room twice, the two copies at shuffled
     positions (ids): at every pixel the GPU's triangle id is the lower id of
