@@ -146,7 +146,10 @@ def alignment_comparison(rm, torch, w, mesh, scan, T0, n_plain=16, reps=3):
         round of evaluations over every start; the starts already fill the
         launch, so speculative batches would only add evaluations);
       * the ablation of the gradient form with one pose per launch, no graph
-        and one workgroup per item (no persistent scheduling)."""
+        and one workgroup per item (no persistent scheduling);
+      * the batched GN alignment against the map meshed without node
+        smoothing (radius 0), to show what that reading of the paper's
+        suggested blurring buys."""
     from paper_1702_06813_amd import align as A
     B = T0.shape[0]
     res = {}
@@ -172,7 +175,7 @@ def alignment_comparison(rm, torch, w, mesh, scan, T0, n_plain=16, reps=3):
         if method == "gn":
             res["batched_error_m_same_starts"] = float(np.median(dtb[:n_plain]))
             res["batched_error_deg_same_starts"] = float(np.degrees(np.median(dab[:n_plain])))
-            tgn = tb
+            tgn, dtb_gn = tb, dtb
     res["iterations"] = 20
     # the paper's plain form, one evaluation per launch, and batched within each alignment
     for form in ("plain", "plain_within"):
@@ -231,6 +234,19 @@ def alignment_comparison(rm, torch, w, mesh, scan, T0, n_plain=16, reps=3):
     res.update({"one_pose_per_launch_grad_scans_per_s": 1.0 / ta,
                 "one_pose_per_launch_grad_error_m_median": float(np.median(dta)),
                 "batched_vs_one_pose_per_launch": ta * B / tgn})
+    # what the node smoothing of the map meshing buys: the same batched GN
+    # alignment against the map meshed without it (smoothing radius 0)
+    parts = [rm.mesh_from_range(torch.from_numpy(d).to(T0.device), w.cam, T, w.stride, w.z_min, w.z_max,
+                                w.max_edge, 0) for T, d in zip(w.views, w.view_depths)]
+    mesh0 = rm.Mesh.concat(parts).prepare()
+    T0b = A.BatchedAligner(mesh0, scan, B, iters=20).run(T0, use_graph=False)
+    dt0, da0 = A.pose_errors(T0b.cpu().numpy(), w.T_true)
+    log(f"batched gn, map meshed without smoothing: median error {np.median(dt0) * 100:.2f} cm "
+        f"{np.degrees(np.median(da0)):.3f} deg, {int((dt0 < 0.02).sum())}/{B} under 2 cm")
+    res.update({"unsmoothed_map_batched_error_m_median": float(np.median(dt0)),
+                "unsmoothed_map_batched_error_deg_median": float(np.degrees(np.median(da0))),
+                "unsmoothed_map_under_2cm": int((dt0 < 0.02).sum()),
+                "smoothed_map_under_2cm": int((dtb_gn < 0.02).sum())})
     return res
 
 
@@ -286,7 +302,9 @@ def trajectory_c5(rm, torch, dev, n_scans=500):
     every scan from exactly 10 cm / 5 deg off its truth, 20 Gauss-Newton
     iterations, 32 scans per launch, one captured graph per batch shape.
     Timed: the whole alignment of all scans (staging copies, graph replays,
-    pose read-back); not timed: generation, meshing, the warm-up pass."""
+    pose read-back); not timed: generation, meshing, the warm-up pass.  Beside
+    it, the paper's plain form (one pose per launch, cost only) on the first
+    12 scans of the walk, for scans/s and errors on different scans."""
     from paper_1702_06813_amd import align as A
     from workloads import configs
     t0 = time.time()
@@ -312,12 +330,26 @@ def trajectory_c5(rm, torch, dev, n_scans=500):
     log(f"trajectory: {len(T) / dt:.0f} scans/s ({launches} cost launches, {len(ta.shapes)} graph shapes); RMSE "
         f"{np.sqrt(np.mean(dt_m ** 2)) * 100:.2f} cm {np.sqrt(np.mean(da ** 2)):.3f} deg (initial "
         f"{np.sqrt(np.mean(d0 ** 2)) * 100:.1f} cm)")
+    # the paper's plain form on different scans of the walk: the first n_plain
+    # scans (all three resolutions), one pose per launch, cost only
+    n_plain = 12
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Tp = [A.plain_align(mesh, scans[j], T0[j], eps=0.1, budget=700)[0] for j in range(n_plain)]
+    tp = (time.perf_counter() - t1) / n_plain
+    dpl = np.array([A.pose_errors(Tp[j], truth[j])[0][0] for j in range(n_plain)])
+    log(f"trajectory, plain form on {n_plain} scans: {1.0 / tp:.2f} scans/s, median {np.median(dpl) * 100:.2f} cm "
+        f"(batched on the same scans: median {np.median(dt_m[:n_plain]) * 100:.2f} cm)")
     return {"scans": len(T), "scans_per_s": len(T) / dt, "wall_s": dt, "cost_launches": int(launches),
             "graph_shapes": len(ta.shapes), "map_tris": int(mesh.n_tris),
             "rmse_m": float(np.sqrt(np.mean(dt_m ** 2))), "rmse_deg": float(np.sqrt(np.mean(da ** 2))),
             "median_error_m": float(np.median(dt_m)), "p90_error_m": float(np.percentile(dt_m, 90)),
             "scans_over_5cm": int((dt_m > 0.05).sum()),
             "initial_rmse_m": float(np.sqrt(np.mean(d0 ** 2))),
+            "plain_form_scans": n_plain, "plain_form_scans_per_s": 1.0 / tp,
+            "plain_form_error_m_median": float(np.median(dpl)),
+            "batched_error_m_median_same_scans": float(np.median(dt_m[:n_plain])),
+            "speedup_vs_plain_form": (len(T) / dt) * tp,
             "paper_context": "the paper aligns scans one second apart at about 2 Hz on a GTX 765M"}
 
 

@@ -203,7 +203,9 @@ int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
 /* Capacity of the per-(pose, screen tile) triangle bins, in entries.  0 (the
  * default) adapts it: the first call of a launch shape sizes the bins from
  * the binning pass and later calls grow them from earlier calls' largest
- * fill.  cap > 0 fixes it and never grows it; a bin that overflows is then
+ * fill, as far as the bins of one call fit in a quarter of the device's
+ * memory (every bin holds the capacity).  cap > 0 fixes it and never grows
+ * it; a bin that overflows is then
  * rasterized from every visible cluster of its pose instead (slower, same
  * result).  cap in 0 .. 2^24, else RM_ERR_INVALID_ARG. */
 int rm_set_bin_cap(rm_ctx* ctx, int32_t cap);
@@ -224,7 +226,10 @@ int rm_set_schedule(rm_ctx* ctx, int32_t mode);
  * the call's own inputs, largest first, skipping shapes the batch cannot use
  * (see rm_set_tile) and stopping at the first shape more than 25% slower than
  * the best so far, and keeps the fastest for later calls of that shape.  With
- * the environment variable RM_LOG set, each choice is printed to stderr. */
+ * the environment variable RM_LOG set, each choice is printed to stderr, and
+ * so is the plan of the first uncaptured call of every launch shape (scans,
+ * poses, triangles and clusters, tile, tile records, schedule, bin capacity
+ * and largest fill, scratch bytes) with any growth of the bins. */
 int rm_autotune(rm_ctx* ctx, int32_t enable);
 /* Current tile choice for a single-scan shape (after autotuning), for
  * reporting: the explicit tile, else the tuned one, else 64x32. */

@@ -42,6 +42,7 @@ struct rm_ctx {
     // every-cluster path)
     int32_t bin_cap = 1024;
     int32_t bin_cap_fixed = 0;
+    int64_t bin_budget = (int64_t)32 << 30;   // largest tile-bin allocation: a quarter of the device memory
     hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bin
     bool bin_pending = false;
     // launch shapes whose bins were sized by a synchronous check after binning
@@ -205,7 +206,6 @@ std::string tile_limit(const BatchDesc& bd0, int tw, int th) {
     return std::string();
 }
 
-constexpr int64_t kMaxBinBytes = (int64_t)32 << 30;   // largest tile-bin allocation
 constexpr int64_t kMinBinCap = 64;                     // the budget never shrinks a bin below this
 
 // Grows the bin capacity when the largest bin of an earlier call (read back
@@ -217,7 +217,7 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
     const int32_t need = ctx->pinned[1];
     int64_t cap = ctx->bin_cap;
     while (cap < need + need / 4 && cap < ((int64_t)1 << 24)) cap *= 2;
-    while (cap > 1024 && n_records * cap * 4 > kMaxBinBytes) cap /= 2;
+    while (cap > 1024 && n_records * cap * 4 > ctx->bin_budget) cap /= 2;
     ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
 }
 
@@ -270,7 +270,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         // the capacity learned so far (or fixed), limited to what this call's records may take
         int64_t cap = fixed_cap ? ctx->bin_cap_fixed : ctx->bin_cap;
         if (!fixed_cap)
-            while (cap > kMinBinCap && R * cap * 4 > kMaxBinBytes) cap /= 2;
+            while (cap > kMinBinCap && R * cap * 4 > ctx->bin_budget) cap /= 2;
         Carve cv;
         // vis_count, vis_tris, bin_max, bin_fill[2], bin fills, order histogram and cursors, queue
         const int64_t n_cnt = 2 * (int64_t)P + 3 + 2 * R + 65;
@@ -363,11 +363,23 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
         ctx->bin_checked.insert(shape);
         const int64_t need = (int64_t)ctx->pinned[2] + (int64_t)ctx->pinned[3];
+        const bool log = getenv("RM_LOG") != nullptr;
+        if (log)
+            fprintf(stderr,
+                    "[rendermap] plan: %d scans, %d poses, %lld triangles (%lld clusters), tile %dx%d, %lld tile "
+                    "records, %s schedule, bin capacity %lld (largest fill %lld), %zu bytes of scratch\n",
+                    bd.n_scans, P, (long long)mesh->n_tris, (long long)C, tw, th, (long long)R,
+                    persistent ? "persistent longest-first" : "one workgroup per item", (long long)cap,
+                    (long long)need, cv.off);
         if (need <= cap) break;
         int64_t grown = cap;
         while (grown < need + need / 4 && grown < ((int64_t)1 << 24)) grown *= 2;
-        while (grown > kMinBinCap && R * grown * 4 > kMaxBinBytes) grown /= 2;
-        if (grown <= cap) break;               // cannot grow: overflowing bins take the slow path
+        while (grown > kMinBinCap && R * grown * 4 > ctx->bin_budget) grown /= 2;
+        if (grown <= cap) {                    // cannot grow: overflowing bins take the slow path
+            if (log) fprintf(stderr, "[rendermap] bins cannot grow past %lld entries\n", (long long)cap);
+            break;
+        }
+        if (log) fprintf(stderr, "[rendermap] bins grown to %lld entries; binning again\n", (long long)grown);
         ctx->bin_cap = (int32_t)std::max<int64_t>(grown, ctx->bin_cap);
     }
     hipEvent_t pe1;
@@ -530,6 +542,11 @@ int rm_ctx_create(int32_t device, rm_ctx** out) {
     c->device = device;
     DeviceGuard g(device);
     noalloc_setup(device);
+    size_t mem_free = 0, mem_total = 0;
+    if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess)
+        c->bin_budget = std::max<int64_t>((int64_t)4 << 30, (int64_t)(mem_total / 4));
+    else
+        (void)hipGetLastError();
     if (hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(nullptr, RM_ERR_DEVICE, "hipHostMalloc failed");
