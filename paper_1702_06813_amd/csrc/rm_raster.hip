@@ -1182,7 +1182,7 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
     bool visible = false;
     uint32_t rect = 0;
     int ntri = 0;
-    float znear = 0.0f;                        // nearest box corner depth (ordering key only)
+    float zkey = 0.0f;                         // farthest box corner depth (ordering key only)
     if (c < n_clusters) {
         const ClusterBounds b = cb[c];
         ntri = b.n_tris;
@@ -1202,7 +1202,7 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
             nfront += Z[k] >= zn;
             nfar += Z[k] > zf;
         }
-        znear = (float)fmax(fmin(fmin(fmin(Z[0], Z[1]), fmin(Z[2], Z[3])), fmin(fmin(Z[4], Z[5]), fmin(Z[6], Z[7]))), zn);
+        zkey = (float)fmax(fmax(fmax(fmax(Z[0], Z[1]), fmax(Z[2], Z[3])), fmax(fmax(Z[4], Z[5]), fmax(Z[6], Z[7]))), zn);
         const double fx = sd.fx, fy = sd.fy, cx = sd.cx, cy = sd.cy;
         double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
         if (nfront > 0 && nfar < 8 && b.n_tris > 0) {
@@ -1251,16 +1251,18 @@ __global__ void __launch_bounds__(kWG) k_cull(BatchDesc bd, const ClusterBounds*
     if (visible) {
         const int64_t slot = (int64_t)pose * n_clusters + base + __popcll(m & ((1ull << lane) - 1ull));
         vis[slot] = make_uint2((uint32_t)c, rect);
-        vis_z[slot] = znear;
+        vis_z[slot] = zkey;
     }
 }
 
 // Near-to-far order of each pose's visible clusters: a counting sort on the
-// logarithm of the nearest box corner depth.  The tile bins are filled in
+// logarithm of the farthest box corner depth.  The tile bins are filled in
 // this order, so the rasterizer meets near surfaces first and its depth
-// snapshot rejects more of what lies behind them.  Only speed depends on the
-// order; a pose with more visible clusters than one workgroup stages keeps
-// the order of the cull.
+// snapshot rejects more of what lies behind them; keying on the far corner
+// puts compact surface clusters before clusters that also hold long
+// free-unknown quads (whose bounds reach far behind their surfaces).  Only
+// speed depends on the order; a pose with more visible clusters than one
+// workgroup stages keeps the order of the cull.
 constexpr int kVisSortWG = 1024;
 constexpr int kVisSortMax = 7680;              // 60 KB of LDS staging
 constexpr int kVisBuckets = 256;
