@@ -294,6 +294,47 @@ def config_throughput(rm, torch, dev, name, steps=10):
             "mode": "cost + gradient" if grad else "cost", "tile": list(tile), "autotuned": name == "wide"}
 
 
+def uneven_stream(rm, torch, dev, steps=5):
+    """Pose-evals/s of the uneven stream: 32 scans cycling 320x240, 640x480
+    and 1280x960 with 16-128 candidates each (2,522 poses) against the
+    2.1M-triangle corridor map, cost + gradient in one launch.  Its 712,110
+    (pose, tile) records are too many for bins holding its fullest tile in
+    the memory budget, so this is the workload of the bin overflow (spill
+    list and exact regions).  W = 3 warm-up calls (the first sizes bins and
+    overflow)."""
+    from workloads import configs
+    t0 = time.time()
+    st = configs.uneven()
+    parts = [rm.mesh_from_range(torch.from_numpy(d).to(dev), st.view_cam, T, st.stride, st.z_min, st.z_max,
+                                st.max_edge, st.smooth_radius) for T, d in zip(st.views, st.view_depths)]
+    mesh = rm.Mesh.concat(parts).prepare()
+    scans = [rm.scan_image(torch.from_numpy(x.depth).to(dev), st.z_min, st.z_max, cam=x.cam) for x in st.scans]
+    counts = [len(x.poses) for x in st.scans]
+    T = torch.from_numpy(np.ascontiguousarray(np.concatenate([x.poses for x in st.scans]).reshape(-1, 12))).to(dev)
+    out = torch.empty((T.shape[0], rm.OUT_STRIDE), dtype=torch.float64, device=dev)
+    ctx = rm.context(dev)
+    try:
+        for _ in range(3):
+            rm.align_cost_grad(mesh, scans, T, 0.1, poses_per_scan=counts, out=out)
+        torch.cuda.synchronize()
+        ctx.profile(True); ctx.profile_read(); ctx.profile_read_binning()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            rm.align_cost_grad(mesh, scans, T, 0.1, poses_per_scan=counts, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / steps
+        n, ms = ctx.profile_read()
+        nb, bms = ctx.profile_read_binning()
+    finally:
+        ctx.profile(False)
+    log(f"uneven stream: {T.shape[0]} poses in {len(scans)} scans, {mesh.n_tris} triangles: {dt * 1e3:.1f} ms per "
+        f"call ({ms / max(n, 1):.1f} rasterizing, {bms / max(nb, 1):.1f} binning), {T.shape[0] / dt:.0f} "
+        f"pose-evals/s (set up in {time.time() - t0:.1f}s)")
+    return {"pose_evals_per_s": T.shape[0] / dt, "ms_per_call": dt * 1e3, "raster_ms": ms / max(n, 1),
+            "bin_ms": bms / max(nb, 1), "poses": int(T.shape[0]), "scans": len(scans), "n_tris": int(mesh.n_tris),
+            "mode": "cost + gradient"}
+
+
 def trajectory_c5(rm, torch, dev, n_scans=500):
     """Scan-to-map alignment of a 500-scan looped walk (0.5 m/s at 2 Hz, 0.25
     m apart) around an 8 x 6 m office room with 24 boxes, scans cycling
@@ -637,6 +678,7 @@ def main():
         res["icp_odometry"] = icp_odometry(rm, torch, dev)
     if not args.no_configs:
         res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in ("tiny", "kinect", "wide")}
+        res["configs"]["uneven"] = uneven_stream(rm, torch, dev)
     if not args.no_trajectory:
         res["trajectory"] = trajectory_c5(rm, torch, dev)
     if not args.no_color:

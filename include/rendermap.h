@@ -200,15 +200,40 @@ const char* rm_last_error(const rm_ctx* ctx);
  * row or column, or 2^31 or more (pose, tile) pairs, returns
  * RM_ERR_UNSUPPORTED. */
 int rm_set_tile(rm_ctx* ctx, int32_t tile_w, int32_t tile_h);
-/* Capacity of the per-(pose, screen tile) triangle bins, in entries.  0 (the
- * default) adapts it: the first call of a launch shape sizes the bins from
- * the binning pass and later calls grow them from earlier calls' largest
- * fill, as far as the bins of one call fit in a quarter of the device's
- * memory (every bin holds the capacity).  cap > 0 fixes it and never grows
- * it; a bin that overflows is then
- * rasterized from every visible cluster of its pose instead (slower, same
- * result).  cap in 0 .. 2^24, else RM_ERR_INVALID_ARG. */
+/* Capacity of the per-(pose, screen tile) triangle bins, in entries: small
+ * footprints fill a bin from its front, large ones (bounding box over 100
+ * px) from its back, each class within its own part of the capacity (the
+ * large part learned from the largest large fill, at most half, and at most
+ * an eighth when the memory budget keeps the capacity below what both parts
+ * want).  0 (the default) adapts it: the first call of a launch shape sizes
+ * the bins from the binning pass and later calls grow them from earlier
+ * calls' largest fills, as far as the bins of one call fit in a quarter of
+ * the device's memory (every bin holds the capacity).  cap > 0 fixes it and
+ * never grows it.  Entries past a bin's part spill to the overflow
+ * (rm_set_bin_pool) when it has room for them, else the tile is rasterized
+ * from every visible cluster of its pose (slower); results are the same
+ * either way.  Each change makes the next call of every launch shape size
+ * its bins again.  cap in 0 .. 2^24, else RM_ERR_INVALID_ARG. */
 int rm_set_bin_cap(rm_ctx* ctx, int32_t cap);
+/* Overflow of the tile bins, for calls whose fullest bins the memory budget
+ * keeps beyond the capacity (many records, uneven fills).  The binning pass
+ * appends the entries past a bin's parts to a spill list (12 bytes each:
+ * triangle, record, slot); each bin that spilled then gets an overflow region
+ * of exactly its fill (4 bytes an entry), laid out like a bin, which its kept
+ * entries and its spilled ones are copied into, and the rasterizer reads it
+ * there.  List and regions share the budget of a quarter of the device's
+ * memory with the bins.
+ *   -1  adaptive (default): overflow joins the calls once a bin has outgrown
+ *       a capacity that could not grow; the first call of a launch shape
+ *       sizes list and regions, later calls grow them from what earlier
+ *       calls asked for
+ *    0  none: bins that outgrow their parts take the every-cluster path
+ *  > 0  a list and regions of exactly this many entries each, never
+ *       resized; bins they cannot hold take the every-cluster path
+ * The allocation-free call has no overflow.  Results do not depend on the
+ * setting.  Each change makes the next call of every launch shape size its
+ * bins again.  entries in -1 .. 2^40, else RM_ERR_INVALID_ARG. */
+int rm_set_bin_pool(rm_ctx* ctx, int64_t entries);
 /* Work scheduling of the rasterizer over (scan, pose, tile) items:
  *   0  automatic: currently 2, measured faster for single- and multi-scan
  *      batches alike
@@ -227,9 +252,13 @@ int rm_set_schedule(rm_ctx* ctx, int32_t mode);
  * (see rm_set_tile) and stopping at the first shape more than 25% slower than
  * the best so far, and keeps the fastest for later calls of that shape.  With
  * the environment variable RM_LOG set, each choice is printed to stderr, and
- * so is the plan of the first uncaptured call of every launch shape (scans,
- * poses, triangles and clusters, tile, tile records, schedule, bin capacity
- * and largest fill, scratch bytes) with any growth of the bins. */
+ * so is the plan of each sizing pass of the first uncaptured call of every
+ * launch shape (scans, poses, triangles and clusters, tile, tile records,
+ * schedule, bin capacity and its large part with the largest fills,
+ * overflow list and region entries with what the spilling bins asked for,
+ * scratch bytes) with any growth of the bins or the overflow; with RM_LOG
+ * set, that call reads the fills back even where capacity and overflow are
+ * fixed. */
 int rm_autotune(rm_ctx* ctx, int32_t enable);
 /* Current tile choice for a single-scan shape (after autotuning), for
  * reporting: the explicit tile, else the tuned one, else 64x32. */

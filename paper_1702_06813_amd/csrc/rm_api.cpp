@@ -37,14 +37,25 @@ struct rm_ctx {
     // timed launches of the rasterizer ([0]) and of the binning kernel ([1])
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[2];
     size_t prof_used[2] = {0, 0};
-    // tile-bin capacity, adapted from the largest bin of earlier calls, unless
-    // fixed by rm_set_bin_cap (then never grown: overflowing bins take the
-    // every-cluster path)
+    // tile-bin capacity, adapted from the largest bins of earlier calls, unless
+    // fixed by rm_set_bin_cap (then never grown), and the part of it for large
+    // footprints (at most half), adapted from the largest large fill
     int32_t bin_cap = 1024;
+    int32_t big_cap = 256;
+    int32_t small_want = 0;           // learned slots for small footprints
     int32_t bin_cap_fixed = 0;
-    int64_t bin_budget = (int64_t)32 << 30;   // largest tile-bin allocation: a quarter of the device memory
-    hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bin
+    int64_t bin_budget = (int64_t)32 << 30;   // bins and overflow together: a quarter of the device memory
+    // overflow (spill list and regions): -1 adaptive, 0 none, > 0 fixed
+    // entries (rm_set_bin_pool); adaptively it takes part in calls once a bin
+    // has outgrown its capacity, sized from what earlier calls spilled
+    int64_t pool_mode = -1;
+    int64_t list_want = 0;            // spill-list entries learned (adaptive)
+    int64_t region_want = 0;          // overflow-region entries learned (adaptive)
+    bool pool_track = false;          // bin with the spilling kernel (it measures what overflow must hold)
+    hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bins
     bool bin_pending = false;
+    bool pool_pending = false;        // the pending readback includes what the call spilled
+    int32_t last_cap_s = 0, last_cap_b = 0;   // bin parts of the call whose readback is pending
     // launch shapes whose bins were sized by a synchronous check after binning
     std::set<std::tuple<int64_t, int, int, int64_t, int>> bin_checked;
     // once a graph has been captured, scratch that it may reference is never freed early
@@ -208,17 +219,75 @@ std::string tile_limit(const BatchDesc& bd0, int tw, int th) {
 
 constexpr int64_t kMinBinCap = 64;                     // the budget never shrinks a bin below this
 
-// Grows the bin capacity when the largest bin of an earlier call (read back
-// asynchronously) did not fit; never while capturing.
+// Pinned readback slots: [1] and [4] largest small and large bin of the last
+// call, [2..3] largest small and large fills of a sizing pass; int64 pairs:
+// [6..7] and [12..13] list and region entries the last call asked for,
+// [8..9], [10..11] and [14..15] list entries, records and region entries of a
+// sizing pass.
+int64_t pinned64(const rm_ctx* ctx, int i) {
+    int64_t v;
+    memcpy(&v, ctx->pinned + i, sizeof(v));
+    return v;
+}
+
+// Overflow entries to learn from a demand of `need`: a quarter more, for the
+// poses of later calls.
+int64_t pool_margin(int64_t need) { return need > 0 ? need + need / 4 + 4096 : 0; }
+
+// Slots for large footprints to learn from a largest large fill of `fb`.
+int64_t big_margin(int64_t fb) { return (fb + fb / 4 + 63) & ~(int64_t)63; }
+
+// Learns bin capacity and large part from the largest small and large fills
+// seen (fs, fb), as far as the bins of n_records fit the budget; true if
+// either grew.
+bool learn_bins(rm_ctx* ctx, int64_t n_records, int64_t fs, int64_t fb) {
+    const int64_t want_b = std::min<int64_t>(big_margin(fb), (int64_t)1 << 23);
+    const int64_t want_s = std::min<int64_t>(fs + fs / 4, (int64_t)1 << 24);
+    int64_t cap = ctx->bin_cap;
+    while (cap < want_s + want_b && cap < ((int64_t)1 << 24)) cap *= 2;
+    while (cap > 1024 && n_records * cap * 4 > ctx->bin_budget) cap /= 2;
+    const bool grew = cap > ctx->bin_cap || want_b > ctx->big_cap || want_s > ctx->small_want;
+    ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
+    ctx->big_cap = (int32_t)std::max<int64_t>(want_b, ctx->big_cap);
+    ctx->small_want = (int32_t)std::max<int64_t>(want_s, ctx->small_want);
+    return grew;
+}
+
+// The part of a capacity of cap for large footprints: what was learned when
+// both parts fit, else at most an eighth (small footprints are the bulk of
+// the entries), and never more than half.
+int64_t big_part(const rm_ctx* ctx, int64_t cap) {
+    const int64_t b = std::min<int64_t>(ctx->big_cap, cap / 2);
+    return (int64_t)ctx->small_want + ctx->big_cap <= cap ? b : std::min<int64_t>(b, cap / 8);
+}
+
+// The capacity a call of n_records gets: the fixed one, or the learned one
+// halved until its bins fit the budget.
+int64_t call_cap(const rm_ctx* ctx, int64_t n_records) {
+    if (ctx->bin_cap_fixed > 0) return ctx->bin_cap_fixed;
+    int64_t cap = ctx->bin_cap;
+    while (cap > kMinBinCap && n_records * cap * 4 > ctx->bin_budget) cap /= 2;
+    return cap;
+}
+
+// Grows the bins when the largest bins of an earlier call (read back
+// asynchronously) did not fit their parts, and the overflow when what the
+// call spilled did not; never while capturing.
 void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
     if (!ctx->bin_pending || capturing(ctx)) return;
     if (hipEventQuery(ctx->bin_ev) != hipSuccess) { (void)hipGetLastError(); return; }
     ctx->bin_pending = false;
-    const int32_t need = ctx->pinned[1];
-    int64_t cap = ctx->bin_cap;
-    while (cap < need + need / 4 && cap < ((int64_t)1 << 24)) cap *= 2;
-    while (cap > 1024 && n_records * cap * 4 > ctx->bin_budget) cap /= 2;
-    ctx->bin_cap = (int32_t)std::max<int64_t>(cap, ctx->bin_cap);
+    const int32_t fs = ctx->pinned[1], fb = ctx->pinned[4];
+    if (ctx->pool_pending) {
+        ctx->pool_pending = false;
+        ctx->list_want = std::max(ctx->list_want, pool_margin(pinned64(ctx, 6)));
+        ctx->region_want = std::max(ctx->region_want, pool_margin(pinned64(ctx, 12)));
+    }
+    if (ctx->bin_cap_fixed == 0) learn_bins(ctx, n_records, fs, fb);
+    if (fs <= ctx->last_cap_s && fb <= ctx->last_cap_b) return;
+    // bins that would still overflow at the next call's capacity spill from then on
+    const int64_t cap = call_cap(ctx, n_records), cap_b = big_part(ctx, cap);
+    if ((fs > cap - cap_b || fb > cap_b) && ctx->pool_mode < 0) ctx->pool_track = true;
 }
 
 // Starts the timing of one launch of kernel k (0 rasterizer, 1 binning) when
@@ -254,32 +323,59 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     const int64_t R = total_records(bd);
     const bool fixed_cap = ctx->bin_cap_fixed > 0;
     adapt_bin_cap(ctx, R);
-    // The first uncaptured call of a launch shape reads the largest bin fill
-    // back right after binning and, if the bins were too small, grows them and
-    // bins again, so that no call of that shape takes the slow every-cluster
-    // path of an overflowing bin; later calls adapt asynchronously.  A fixed
-    // capacity (rm_set_bin_cap) or a fixed scratch buffer is never grown.
+    // The first uncaptured call of a launch shape reads the largest bin fills
+    // back right after binning and, if the bins were too small, grows them
+    // (or, where the budget stops that, sizes the overflow) and bins again,
+    // so that no call of that shape takes the slow every-cluster path of an
+    // overflowing bin; later calls adapt asynchronously.  A fixed capacity
+    // (rm_set_bin_cap) is never grown, a fixed overflow never resized, and
+    // the allocation-free call has neither growth nor overflow.
     const auto shape = std::make_tuple(R, tw, th, mesh->n_tris, P);
-    const bool check = !fixed_cap && !arena.fixed && !capturing(ctx) && ctx->bin_checked.count(shape) == 0;
+    const bool pool_adaptive = ctx->pool_mode < 0 && !arena.fixed;
+    const bool log = getenv("RM_LOG") != nullptr;  // the sizing pass then also reports fixed settings
+    const bool check = !arena.fixed && !capturing(ctx) && ctx->bin_checked.count(shape) == 0 &&
+                       (!fixed_cap || pool_adaptive || log);
     const bool persistent = ctx->schedule != 1;
     RasterArgs a;
     int32_t* vis_count = nullptr;
     int32_t* vis_tris = nullptr;
     int32_t* bin_max = nullptr;
+    int64_t cap = 0, cap_b = 0;
     for (int attempt = 0;; ++attempt) {
         // the capacity learned so far (or fixed), limited to what this call's records may take
-        int64_t cap = fixed_cap ? ctx->bin_cap_fixed : ctx->bin_cap;
-        if (!fixed_cap)
-            while (cap > kMinBinCap && R * cap * 4 > ctx->bin_budget) cap /= 2;
+        cap = call_cap(ctx, R);
+        // overflow: spill-list entries (12 bytes) and region entries (4
+        // bytes), as learned, scaled down to what the budget leaves beside the bins
+        int64_t spill_cap = 0, pool_cap = 0;
+        if (!arena.fixed && ctx->pool_mode > 0) {
+            spill_cap = pool_cap = ctx->pool_mode;
+        } else if (pool_adaptive) {
+            const double room = (double)std::max<int64_t>(0, ctx->bin_budget - R * cap * 4);
+            const double want = 12.0 * (double)ctx->list_want + 4.0 * (double)ctx->region_want;
+            const double f = want > room ? room / want : 1.0;
+            spill_cap = (int64_t)((double)ctx->list_want * f);
+            pool_cap = (int64_t)((double)ctx->region_want * f);
+        }
+        spill_cap = std::min<int64_t>(spill_cap, 0xfffffffell);
+        // the spilling kernel also measures what overflow must hold: always in a sizing pass
+        const bool track = !arena.fixed && (check || spill_cap > 0 || (ctx->pool_track && ctx->pool_mode != 0));
         Carve cv;
-        // vis_count, vis_tris, bin_max, bin_fill[2], bin fills, order histogram and cursors, queue
-        const int64_t n_cnt = 2 * (int64_t)P + 3 + 2 * R + 65;
+        // vis_count, vis_tris, bin_max[2], bin_fill[2], bin fills, order histogram and cursors, queue
+        const int64_t n_cnt = 2 * (int64_t)P + 4 + 2 * R + 65;
         const size_t o_cnt = cv.take<int32_t>(n_cnt);
         const size_t o_ord = cv.take<int32_t>(persistent ? R : 1);
         const size_t o_vis = cv.take<uint2>((int64_t)P * C);
         const size_t o_visz = cv.take<float>((int64_t)P * C);
         const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
         const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
+        // spill counters [5] (u64) and lost flags [R], zeroed; region offsets; spilled
+        // records; spill list; regions
+        const int64_t n_sz = track ? 10 + R : 0;
+        const size_t o_sz = track ? cv.take<int32_t>(n_sz) : 0;
+        const size_t o_poff = track ? cv.take<int64_t>(R) : 0;
+        const size_t o_srec = track ? cv.take<int32_t>(R) : 0;
+        const size_t o_spill = spill_cap > 0 ? cv.take<uint3>(spill_cap) : 0;
+        const size_t o_pool = pool_cap > 0 ? cv.take<uint32_t>(pool_cap) : 0;
         const size_t o_bin = cv.off;
         char* base = nullptr;
         if (arena.fixed) {
@@ -297,11 +393,12 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
             if (rc) return rc;
             base = static_cast<char*>(ctx->scratch);
         }
+        cap_b = big_part(ctx, cap);
         auto at = [&](size_t off) { return base + off; };
         vis_count = reinterpret_cast<int32_t*>(at(o_cnt));
         vis_tris = vis_count + P;
         bin_max = vis_tris + P;
-        int32_t* bin_fill = bin_max + 1;
+        int32_t* bin_fill = bin_max + 2;
         int32_t* bin_small = bin_fill + 2;
         int32_t* bin_big = bin_small + R;
         int32_t* hist = bin_big + R;
@@ -316,6 +413,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
                                                                  prepared_normals_offset(mesh->n_tris))
                                 : nullptr;
         RM_HIP(ctx, launch_zero_i32(ctx->stream, vis_count, n_cnt));
+        if (track) RM_HIP(ctx, launch_zero_i32(ctx->stream, reinterpret_cast<int32_t*>(at(o_sz)), n_sz));
         uint2* vis = reinterpret_cast<uint2*>(at(o_vis));
         float* vis_z = reinterpret_cast<float*>(at(o_visz));
         RM_HIP(ctx, launch_cull(ctx->stream, bd, cb, (int32_t)C, T_wc, vis, vis_z, vis_count, vis_tris));
@@ -334,8 +432,18 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.bin_small = bin_small;
         a.bin_big = bin_big;
         a.bin_max = bin_max;
-        a.bin_fill = check && attempt == 0 ? bin_fill : nullptr;
+        a.bin_fill = check ? bin_fill : nullptr;
         a.bin_cap = (int32_t)cap;
+        a.bin_big_cap = (int32_t)cap_b;
+        a.spill_top = track ? reinterpret_cast<unsigned long long*>(at(o_sz)) : nullptr;
+        a.spill_lost = track ? reinterpret_cast<int32_t*>(at(o_sz)) + 10 : nullptr;
+        a.spill_recs = track ? reinterpret_cast<int32_t*>(at(o_srec)) : nullptr;
+        a.pool_off = track ? reinterpret_cast<int64_t*>(at(o_poff)) : nullptr;
+        // (a list without regions would place nothing: keep neither)
+        a.spill = spill_cap > 0 && pool_cap > 0 ? reinterpret_cast<uint3*>(at(o_spill)) : nullptr;
+        a.pool = spill_cap > 0 && pool_cap > 0 ? reinterpret_cast<uint32_t*>(at(o_pool)) : nullptr;
+        a.spill_cap = a.spill ? spill_cap : 0;
+        a.pool_cap = a.pool ? pool_cap : 0;
         a.order = nullptr;
         a.queue = hist + 64;
         a.n_order = (int32_t)R;
@@ -351,36 +459,66 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         int prc = prof_begin(ctx, 1, arena.fixed != nullptr, &be1);
         if (prc) return prc;
         RM_HIP(ctx, launch_bin(ctx->stream, bd, a));
+        if (track) RM_HIP(ctx, launch_overflow(ctx->stream, a, R));
         if (be1) RM_HIP(ctx, hipEventRecord(be1, ctx->stream));
         if (persistent) {
             int32_t* order = reinterpret_cast<int32_t*>(at(o_ord));
             RM_HIP(ctx, launch_order(ctx->stream, bd, bin_small, bin_big, R, hist, order));
             a.order = order;
         }
-        if (!check || attempt > 0) break;
+        if (!check) break;
         RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 2, bin_fill, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 8, a.spill_top, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 10, a.spill_top + 2, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 14, a.spill_top + 4, sizeof(int64_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
         RM_HIP(ctx, hipStreamSynchronize(ctx->stream));
         ctx->bin_checked.insert(shape);
-        const int64_t need = (int64_t)ctx->pinned[2] + (int64_t)ctx->pinned[3];
-        const bool log = getenv("RM_LOG") != nullptr;
+        const int64_t fs = ctx->pinned[2], fb = ctx->pinned[3];
+        const int64_t spilled = pinned64(ctx, 8), spill_recs = pinned64(ctx, 10), filled = pinned64(ctx, 14);
         if (log)
             fprintf(stderr,
                     "[rendermap] plan: %d scans, %d poses, %lld triangles (%lld clusters), tile %dx%d, %lld tile "
-                    "records, %s schedule, bin capacity %lld (largest fill %lld), %zu bytes of scratch\n",
+                    "records, %s schedule, bin capacity %lld (%lld for large footprints; largest fills %lld "
+                    "small, %lld large), overflow list %lld and regions %lld entries (%lld bins spill %lld of "
+                    "%lld entries), %zu bytes of scratch\n",
                     bd.n_scans, P, (long long)mesh->n_tris, (long long)C, tw, th, (long long)R,
                     persistent ? "persistent longest-first" : "one workgroup per item", (long long)cap,
-                    (long long)need, cv.off);
-        if (need <= cap) break;
-        int64_t grown = cap;
-        while (grown < need + need / 4 && grown < ((int64_t)1 << 24)) grown *= 2;
-        while (grown > kMinBinCap && R * grown * 4 > ctx->bin_budget) grown /= 2;
-        if (grown <= cap) {                    // cannot grow: overflowing bins take the slow path
-            if (log) fprintf(stderr, "[rendermap] bins cannot grow past %lld entries\n", (long long)cap);
+                    (long long)cap_b, (long long)fs, (long long)fb, (long long)a.spill_cap, (long long)a.pool_cap,
+                    (long long)spill_recs, (long long)spilled, (long long)filled, cv.off);
+        if ((fs <= cap - cap_b && fb <= cap_b) || attempt >= 2) break;
+        if (!fixed_cap && learn_bins(ctx, R, fs, fb)) {
+            const int64_t c2 = call_cap(ctx, R), b2 = big_part(ctx, c2);
+            if (c2 > cap || b2 != cap_b) {
+                if (log)
+                    fprintf(stderr, "[rendermap] bins grown to %lld entries (%lld large); binning again\n",
+                            (long long)c2, (long long)b2);
+                if (pool_adaptive && (fs > c2 - b2 || fb > b2)) ctx->pool_track = true;
+                continue;
+            }
+        }
+        // the bins cannot grow: what outgrows them spills
+        if (pool_adaptive) ctx->pool_track = true;
+        const bool placed = spilled <= a.spill_cap && filled <= a.pool_cap;
+        if (placed || !pool_adaptive) {
+            if (!placed && log)
+                fprintf(stderr, "[rendermap] bins whose overflow does not fit take the every-cluster path\n");
             break;
         }
-        if (log) fprintf(stderr, "[rendermap] bins grown to %lld entries; binning again\n", (long long)grown);
-        ctx->bin_cap = (int32_t)std::max<int64_t>(grown, ctx->bin_cap);
+        const int64_t lw = std::max(ctx->list_want, pool_margin(spilled));
+        const int64_t rw = std::max(ctx->region_want, pool_margin(filled));
+        if (lw == ctx->list_want && rw == ctx->region_want) {
+            if (log) fprintf(stderr, "[rendermap] the budget leaves the overflow no more room\n");
+            break;
+        }
+        ctx->list_want = lw;
+        ctx->region_want = rw;
+        if (log)
+            fprintf(stderr, "[rendermap] overflow sized to %lld list and %lld region entries; binning again\n",
+                    (long long)lw, (long long)rw);
     }
     hipEvent_t pe1;
     {
@@ -394,8 +532,19 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
     if (!capturing(ctx) && !ctx->bin_pending && !arena.fixed) {
         if (!ctx->bin_ev) RM_HIP(ctx, hipEventCreateWithFlags(&ctx->bin_ev, hipEventDisableTiming));
         RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, bin_max, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 4, bin_max + 1, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        if (a.spill_top) {
+            RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 6, a.spill_top, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            RM_HIP(ctx, hipMemcpyAsync(ctx->pinned + 12, a.spill_top + 4, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+        }
         RM_HIP(ctx, hipEventRecord(ctx->bin_ev, ctx->stream));
         ctx->bin_pending = true;
+        ctx->pool_pending = a.spill_top != nullptr;
+        ctx->last_cap_s = (int32_t)(cap - cap_b);
+        ctx->last_cap_b = (int32_t)cap_b;
     }
     return RM_OK;
 }
@@ -615,6 +764,17 @@ int rm_set_bin_cap(rm_ctx* ctx, int32_t cap) {
     ctx->err.clear();
     if (cap < 0 || cap > (1 << 24)) return fail(ctx, RM_ERR_INVALID_ARG, "bin capacity %d outside 0..2^24", cap);
     ctx->bin_cap_fixed = cap;
+    ctx->bin_checked.clear();         // the next call of each shape sizes its bins again
+    return RM_OK;
+}
+
+int rm_set_bin_pool(rm_ctx* ctx, int64_t entries) {
+    if (!ctx) return fail(nullptr, RM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    if (entries < -1 || entries > ((int64_t)1 << 40))
+        return fail(ctx, RM_ERR_INVALID_ARG, "overflow pool of %lld entries outside -1..2^40", (long long)entries);
+    ctx->pool_mode = entries;
+    ctx->bin_checked.clear();
     return RM_OK;
 }
 

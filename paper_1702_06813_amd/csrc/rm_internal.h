@@ -67,9 +67,27 @@ struct RasterArgs {
                                  // small footprints from the front, large ones from the back
     int32_t* bin_small;          // [n_records] small entries appended (may exceed bin_cap)
     int32_t* bin_big;            // [n_records] large entries appended
-    int32_t* bin_max;            // device scalar: largest bin fill of the call
+    int32_t* bin_max;            // device [2]: largest small and large fill of the call's bins
     int32_t* bin_fill;           // device [2] or null: largest small and large fill reserved by the binning pass
     int32_t bin_cap;
+    int32_t bin_big_cap;         // slots of a bin for large footprints (its back); the rest for small ones
+    // Overflow (spill_top == null: none, and a bin that outgrows a part of
+    // its capacity takes the every-cluster path; spill == null: counted only,
+    // every spilling record is lost).  The binning pass writes entries past
+    // a bin's parts to the spill list as (triangle, record, slot | large <<
+    // 31); each record that spilled gets a region in pool for all its
+    // entries, laid out like a bin of exactly its fill, unless the list ran
+    // out of room for it (spill_lost) or the regions did.
+    uint3* spill;                // [spill_cap]
+    int64_t spill_cap;           // list entries, < 2^32 - 1
+    unsigned long long* spill_top;  // device [5], zeroed: list entries asked for, region cursor, records
+                                    // spilled, spill_cap minus the start of the first list range that
+                                    // crossed the end, region entries asked for
+    int32_t* spill_lost;         // [n_records], zeroed
+    int32_t* spill_recs;         // [n_records] records that spilled, -1 where without a region
+    uint32_t* pool;              // [pool_cap] overflow regions
+    int64_t pool_cap;
+    int64_t* pool_off;           // [n_records] start of the record's region, -1: none
     const int32_t* order;        // null: one workgroup per item; else record indices, longest first
     int32_t* queue;              // device counter of taken items (persistent scheduling)
     int32_t n_order;
@@ -102,6 +120,9 @@ hipError_t launch_cull(hipStream_t st, const BatchDesc& bd, const ClusterBounds*
 hipError_t launch_vis_sort(hipStream_t st, const BatchDesc& bd, int32_t n_clusters, const int32_t* vis_count,
                            const float* vis_z, uint2* vis);
 hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a);
+// After a spilling binning pass: overflow regions for the records that
+// spilled, then the spilled entries placed in them.
+hipError_t launch_overflow(hipStream_t st, const RasterArgs& a, int64_t n_records);
 hipError_t launch_raster(hipStream_t st, const BatchDesc& bd, const RasterArgs& a, int mode);
 // Longest-first order of the records of a binned call: counting sort of the
 // records by log2 of their bin fill, descending.  hist: 32 zeroed counters.

@@ -577,21 +577,36 @@ __device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
 // the two size classes are aggregated in LDS over the cluster's tile
 // rectangle, then reserved with one global atomic per (workgroup, tile,
 // class).  Small footprints fill a bin from the front, large ones from the
-// back, so that the tile pass sees triangles of similar cost together.
+// back, so that the tile pass sees triangles of similar cost together; each
+// class has its own part of the bin (bin_cap - bin_big_cap small slots,
+// bin_big_cap large ones), so the two never overwrite each other.
+//
+// SPILL = true: entries past their class's part are not dropped but written
+// to the spill list with their record and slot, for k_spill_scatter to place
+// in the record's overflow region.  A band's spilled entries take one range
+// of the list (offsets within it from an LDS counter, the range from one
+// global atomic); a band whose range does not fit marks its spilling
+// records lost instead.
 constexpr float kBigFootprint = 100.0f;    // bounding box area widened by 2 px per side, px
+constexpr uint32_t kNoSpill = 0xffffffffu; // marks a tile class of the band that did not spill
+constexpr uint32_t kBigSlot = 0x80000000u; // slot code of a large entry in the spill list
 
-template <int TW, int TH>
+template <int TW, int TH, bool SPILL>
 __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t table_n) {
     // per tile of a band of a cluster's rectangle: small count | large count
-    // << 16 (then cursors), and the two reservations.  table_n = the largest
-    // tile grid of the launch, at most kBinTable, so that the LDS size follows
-    // the images of the call; a rectangle with more tiles is binned in bands
-    // of whole tile rows (table_n >= its width: rows hold at most
-    // kMaxTileGrid <= kBinTable tiles).
+    // << 16 (then cursors), the two reservations and, with SPILL, the two
+    // spill-list bases.  table_n = the largest tile grid of the launch, at
+    // most kBinTable, so that the LDS size follows the images of the call; a
+    // rectangle with more tiles is binned in bands of whole tile rows
+    // (table_n >= its width: rows hold at most kMaxTileGrid <= kBinTable tiles).
     extern __shared__ uint32_t tables[];
     uint32_t* tcnt = tables;
     uint32_t* tbs = tables + table_n;
     uint32_t* tbb = tables + 2 * table_n;
+    uint32_t* tss = tables + 3 * table_n;    // spill offsets within the band's range
+    uint32_t* tsb = tables + 4 * table_n;
+    __shared__ uint32_t band_spill;            // entries the band spills, then whether its range fits
+    __shared__ unsigned long long band_base;
     const int pose = blockIdx.y;
     const int nvis = a.vis_count[pose];
     const ScanDesc& sd = bd.s[pose_scan(bd, pose)];
@@ -602,6 +617,7 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
     const int ntile = sd.tiles_x * sd.tiles_y;
     const int64_t rec0 = sd.rec_off + (int64_t)pl * ntile;
     const uint32_t cap = (uint32_t)a.bin_cap;
+    const uint32_t cap_b = (uint32_t)a.bin_big_cap, cap_s = cap - cap_b;
     for (int k = blockIdx.x; k < nvis; k += gridDim.x) {
         const uint2 e = a.vis[(int64_t)pose * a.n_clusters + k];
         const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
@@ -691,21 +707,39 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
                             atomicAdd(&tcnt[(ty0 + r - by0) * rw + (tx0 + c - rx0)], inc);
                 }
             }
+            if (SPILL && threadIdx.x == 0) band_spill = 0;
             __syncthreads();
             int fs = 0, fb = 0;                    // largest fills this thread reserved
             for (int i = threadIdx.x; i < nb; i += kWG) {
                 const uint32_t n = tcnt[i];
                 if (n) {
                     const int tile = (by0 + i / rw) * sd.tiles_x + rx0 + i % rw;
+                    const int64_t rec = rec0 + tile;
                     if (n & 0xffffu) {
-                        tbs[i] = (uint32_t)atomicAdd(a.bin_small + rec0 + tile, (int)(n & 0xffffu));
-                        fs = max(fs, (int)(tbs[i] + (n & 0xffffu)));
+                        const uint32_t s0 = (uint32_t)atomicAdd(a.bin_small + rec, (int)(n & 0xffffu));
+                        tbs[i] = s0;
+                        fs = max(fs, (int)(s0 + (n & 0xffffu)));
+                        if (SPILL) {
+                            const uint32_t e = s0 + (n & 0xffffu);
+                            tss[i] = e > cap_s ? atomicAdd(&band_spill, e - max(s0, cap_s)) : kNoSpill;
+                        }
+                    } else if (SPILL) {
+                        tss[i] = kNoSpill;
                     }
                     if (n >> 16) {
-                        tbb[i] = (uint32_t)atomicAdd(a.bin_big + rec0 + tile, (int)(n >> 16));
-                        fb = max(fb, (int)(tbb[i] + (n >> 16)));
+                        const uint32_t b0 = (uint32_t)atomicAdd(a.bin_big + rec, (int)(n >> 16));
+                        tbb[i] = b0;
+                        fb = max(fb, (int)(b0 + (n >> 16)));
+                        if (SPILL) {
+                            const uint32_t e = b0 + (n >> 16);
+                            tsb[i] = e > cap_b ? atomicAdd(&band_spill, e - max(b0, cap_b)) : kNoSpill;
+                        }
+                    } else if (SPILL) {
+                        tsb[i] = kNoSpill;
                     }
                     tcnt[i] = 0;
+                } else if (SPILL) {
+                    tss[i] = tsb[i] = kNoSpill;
                 }
             }
             if (a.bin_fill) {                      // only when the host sizes the bins of a new shape
@@ -720,16 +754,47 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
                 }
             }
             __syncthreads();
+            if (SPILL) {
+                // one range of the list for the band; if it does not fit,
+                // the records that spilled here are lost
+                if (threadIdx.x == 0 && band_spill) {
+                    const unsigned long long sp = atomicAdd(a.spill_top, (unsigned long long)band_spill);
+                    const unsigned long long cap_l = (unsigned long long)a.spill_cap;
+                    band_base = sp;
+                    band_spill = sp + band_spill <= cap_l ? 1u : 2u;
+                    // a range that crosses the end of the list leaves its part
+                    // below the end unwritten: the list is valid below its start
+                    if (sp < cap_l && band_spill == 2u) atomicMax(a.spill_top + 3, cap_l - sp);
+                }
+                __syncthreads();
+                if (band_spill == 2u)
+                    for (int i = threadIdx.x; i < nb; i += kWG)
+                        if (tss[i] != kNoSpill || tsb[i] != kNoSpill)
+                            a.spill_lost[rec0 + (by0 + i / rw) * sd.tiles_x + rx0 + i % rw] = 1;
+            }
+            const bool band_ok = !SPILL || band_spill == 1u;
+            const uint32_t sbase = SPILL ? (uint32_t)band_base : 0u;
             auto put = [&](int tx, int ty) {
                 const int li = (ty - by0) * rw + (tx - rx0);
                 const uint32_t old = atomicAdd(&tcnt[li], inc);
-                uint32_t* bin = a.bins + (rec0 + ty * sd.tiles_x + tx) * (int64_t)cap;
+                const int64_t rec = rec0 + ty * sd.tiles_x + tx;
+                uint32_t* bin = a.bins + rec * (int64_t)cap;
                 if (big) {
                     const uint32_t slot = tbb[li] + (old >> 16);
-                    if (slot < cap) bin[cap - 1 - slot] = (uint32_t)t;
+                    if (slot < cap_b) {
+                        bin[cap - 1 - slot] = (uint32_t)t;
+                    } else if (SPILL && band_ok) {
+                        const uint32_t j = sbase + tsb[li] + (slot - max(tbb[li], cap_b));
+                        a.spill[j] = make_uint3((uint32_t)t, (uint32_t)rec, slot | kBigSlot);
+                    }
                 } else {
                     const uint32_t slot = tbs[li] + (old & 0xffffu);
-                    if (slot < cap) bin[slot] = (uint32_t)t;
+                    if (slot < cap_s) {
+                        bin[slot] = (uint32_t)t;
+                    } else if (SPILL && band_ok) {
+                        const uint32_t j = sbase + tss[li] + (slot - max(tbs[li], cap_s));
+                        a.spill[j] = make_uint3((uint32_t)t, (uint32_t)rec, slot);
+                    }
                 }
             };
             if (masked) {
@@ -750,6 +815,76 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
             __syncthreads();                   // the put cursors of this band are no longer read
             for (int i = threadIdx.x; i < brows * rw; i += kWG) tcnt[i] = 0;
         }
+    }
+}
+
+// One thread per record: a record whose bin spilled gets an overflow region
+// for all its entries (laid out like a bin of exactly its fill: small
+// entries ascending from the start, large ones descending from the end),
+// unless its spill was lost or the regions are full.  spill_top[1] is the
+// region cursor, spill_top[2] counts the records that spilled and
+// spill_top[4] totals their fills (what the regions would need); each
+// region's record is listed in spill_recs for k_region_fill.  Regions are
+// handed out in the order the atomics land; results do not depend on where
+// they lie.
+__global__ void __launch_bounds__(kWG) k_region_alloc(RasterArgs a, int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (r >= n) return;
+    const int ns = a.bin_small[r], nb = a.bin_big[r];
+    int64_t off = -1;
+    if (ns > a.bin_cap - a.bin_big_cap || nb > a.bin_big_cap) {
+        const unsigned long long k = atomicAdd(a.spill_top + 2, 1ull);
+        atomicAdd(a.spill_top + 4, (unsigned long long)(ns + nb));
+        if (!a.spill_lost[r]) {
+            const unsigned long long o = atomicAdd(a.spill_top + 1, (unsigned long long)(ns + nb));
+            if (o + (unsigned long long)(ns + nb) <= (unsigned long long)a.pool_cap) {
+                off = (int64_t)o;
+                a.spill_recs[k] = (int32_t)r;
+            } else {
+                a.spill_recs[k] = -1;
+            }
+        } else {
+            a.spill_recs[k] = -1;
+        }
+    }
+    a.pool_off[r] = off;
+}
+
+// One workgroup per listed record at a time: copies the entries its bin
+// kept (the small part's front, the large part's back) into its region.
+__global__ void __launch_bounds__(kWG) k_region_fill(RasterArgs a) {
+    const unsigned long long n = a.spill_top[2];
+    const int cap_b = a.bin_big_cap, cap_s = a.bin_cap - cap_b;
+    for (unsigned long long k = blockIdx.x; k < n; k += gridDim.x) {
+        const int32_t r = a.spill_recs[k];
+        if (r < 0) continue;
+        const int ns = a.bin_small[r], nb = a.bin_big[r], cnt = ns + nb;
+        const uint32_t* bin = a.bins + (int64_t)r * a.bin_cap;
+        uint32_t* reg = a.pool + a.pool_off[r];
+        const int ks = min(ns, cap_s), kb = min(nb, cap_b);
+        for (int i = threadIdx.x; i < ks + kb; i += kWG) {
+            if (i < ks) reg[i] = bin[i];
+            else reg[cnt - 1 - (i - ks)] = bin[a.bin_cap - 1 - (i - ks)];
+        }
+    }
+}
+
+// Places each spilled entry at its slot in its record's region (entries of
+// records without a region stay out).  Every entry below the start of the
+// first range that crossed the end of the list was written by this call.
+__global__ void __launch_bounds__(kWG) k_spill_scatter(RasterArgs a, int64_t n_records) {
+    const unsigned long long cap_l = (unsigned long long)a.spill_cap;
+    const unsigned long long n = min(a.spill_top[0], cap_l - a.spill_top[3]);
+    for (unsigned long long j = (unsigned long long)blockIdx.x * kWG + threadIdx.x; j < n;
+         j += (unsigned long long)gridDim.x * kWG) {
+        const uint3 e = a.spill[j];
+        if ((int64_t)e.y >= n_records) continue;      // (never: each entry names a record of the call)
+        const int64_t off = a.pool_off[e.y];
+        if (off < 0) continue;
+        const int cnt = a.bin_small[e.y] + a.bin_big[e.y];
+        const int slot = (int)(e.z & ~kBigSlot);
+        const int at = e.z & kBigSlot ? cnt - 1 - slot : slot;
+        if (at >= 0 && at < cnt) a.pool[off + at] = e.x;
     }
 }
 
@@ -822,8 +957,16 @@ __device__ __forceinline__ void decode_rec(const BatchDesc& bd, int64_t rec, Ite
     it.rec = rec;
 }
 
+// A pointer whose value is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ const uint32_t* uniform_ptr(const uint32_t* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<const uint32_t*>((uint64_t)hi << 32 | lo);
+}
+
 // One (scan, pose, tile) item: rasterization rounds, resolve, tile record.
-template <int TW, int TH, int MODE>
+template <int TW, int TH, int MODE, bool OVF>
 __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs& a, const ItemInfo& it,
                                           uint64_t* keys, Queues& q, float (*red)[kRecFields]) {
     const ScanDesc& sd = bd.s[it.scan];
@@ -843,24 +986,33 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
     PoseF P;
     load_pose(a.T_wc + 12 * (int64_t)it.pose, P);
     const int ns = a.bin_small[it.rec], nb = a.bin_big[it.rec];
-    if (tid == 0) atomicMax(a.bin_max, ns + nb);
+    if (tid < 2) atomicMax(a.bin_max + tid, tid ? nb : ns);    // one instruction, two lanes
 
     // Rounds of kWG triangles: from the (pose, tile) bin, large footprints
     // (held at its back) before small ones (at its front), so that near
-    // surfaces reach the depth snapshot early; or, if the bin overflowed its
-    // capacity, every triangle of every visible cluster of the pose (slower,
-    // same result).
-    const bool use_bin = ns + nb <= a.bin_cap;
+    // surfaces reach the depth snapshot early.  A bin that outgrew a part of
+    // its capacity is read from its overflow region, which holds all its
+    // entries in the same layout; without one, the tile takes every triangle
+    // of every visible cluster of the pose (slower, same result).
+    // (OVF: the call has overflow regions; the kernel without them is
+    // compiled apart, as the mere presence of the region lookup costs the
+    // common case about half a percent)
+    const bool fits = ns <= a.bin_cap - a.bin_big_cap && nb <= a.bin_big_cap;
+    const int64_t poff = OVF && !fits ? a.pool_off[it.rec] : -1;
+    const bool use_bin = fits || poff >= 0;
     const int nvis = a.vis_count[it.pose];
     const uint2* vis = a.vis + (int64_t)it.pose * a.n_clusters;
-    const uint32_t* bin = a.bins + it.rec * (int64_t)a.bin_cap;
+    // (uniform over the workgroup: kept in scalar registers for the gather)
+    const uint32_t* bin = OVF ? uniform_ptr(poff >= 0 ? a.pool + poff : a.bins + it.rec * (int64_t)a.bin_cap)
+                              : a.bins + it.rec * (int64_t)a.bin_cap;
+    const int bcap = OVF ? __builtin_amdgcn_readfirstlane(poff >= 0 ? ns + nb : a.bin_cap) : a.bin_cap;
     const int nr = use_bin ? (ns + nb + kWG - 1) / kWG : nvis;
     auto entry = [&](int r) -> int32_t {
         if (r >= nr) return -1;
         if (use_bin) {
             const int i = r * kWG + tid;
             if (i >= ns + nb) return -1;
-            return (int32_t)(i < nb ? bin[a.bin_cap - 1 - i] : bin[i - nb]);
+            return (int32_t)(i < nb ? bin[bcap - 1 - i] : bin[i - nb]);
         }
         const int64_t t = (int64_t)vis[r].x * kClusterTris + tid;
         return t < a.n_tris ? (int32_t)t : -1;
@@ -1133,7 +1285,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
 // order, persistent workgroups that take the next item of the order (longest
 // first) from a global counter until it runs past the end; every workgroup
 // reaches that exit.
-template <int TW, int TH, int MODE>
+template <int TW, int TH, int MODE, bool OVF>
 __global__ void __launch_bounds__(kWG, 4) k_raster(BatchDesc bd, RasterArgs a) {
     __shared__ uint64_t keys[TW * TH];
     __shared__ Queues q;
@@ -1141,7 +1293,7 @@ __global__ void __launch_bounds__(kWG, 4) k_raster(BatchDesc bd, RasterArgs a) {
     if (!a.order) {
         ItemInfo it;
         if (!decode_item(bd, it)) return;
-        tile_pass<TW, TH, MODE>(bd, a, it, keys, q, red);
+        tile_pass<TW, TH, MODE, OVF>(bd, a, it, keys, q, red);
         return;
     }
     __shared__ int slot;
@@ -1153,7 +1305,7 @@ __global__ void __launch_bounds__(kWG, 4) k_raster(BatchDesc bd, RasterArgs a) {
         if (k >= a.n_order) return;
         ItemInfo it;
         decode_rec(bd, a.order[k], it);
-        tile_pass<TW, TH, MODE>(bd, a, it, keys, q, red);
+        tile_pass<TW, TH, MODE, OVF>(bd, a, it, keys, q, red);
     }
 }
 
@@ -1391,15 +1543,24 @@ __global__ void __launch_bounds__(kRecFields * kRedSplit) k_reduce(BatchDesc bd,
     }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool SPILL>
 hipError_t launch_bin_t(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
     const dim3 grid((unsigned)std::min(a.n_clusters > 0 ? a.n_clusters : 1, 256), (unsigned)bd.n_poses);
     int32_t n = 1;
     for (int s = 0; s < bd.n_scans; ++s) n = std::max(n, bd.s[s].tiles_x * bd.s[s].tiles_y);
     n = std::min(n, kBinTable);
     static_assert(kMaxTileGrid <= kBinTable, "a row of tiles must fit one binning band");
-    hipLaunchKernelGGL((k_bin<TW, TH>), grid, dim3(kWG), 3 * sizeof(uint32_t) * (size_t)n, st, bd, a, n);
+    const size_t lds = (SPILL ? 5 : 3) * sizeof(uint32_t) * (size_t)n;
+    hipLaunchKernelGGL((k_bin<TW, TH, SPILL>), grid, dim3(kWG), lds, st, bd, a, n);
     return hipGetLastError();
+}
+
+template <bool SPILL>
+hipError_t launch_bin_shape(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
+    if (bd.tile_w == 8 && bd.tile_h == 8) return launch_bin_t<8, 8, SPILL>(st, bd, a);
+    if (bd.tile_w == 16 && bd.tile_h == 16) return launch_bin_t<16, 16, SPILL>(st, bd, a);
+    if (bd.tile_w == 64 && bd.tile_h == 32) return launch_bin_t<64, 32, SPILL>(st, bd, a);
+    return launch_bin_t<32, 32, SPILL>(st, bd, a);
 }
 
 // ------------------------------------------------------------------ longest-first order
@@ -1468,10 +1629,17 @@ hipError_t launch_raster_t(hipStream_t st, const BatchDesc& bd, const RasterArgs
     const int64_t chunk = (bd.n_items + 7) / 8;
     const dim3 grid(a.order ? (unsigned)std::min<int64_t>(persistent_grid(TW, TH, mode), a.n_order)
                             : (unsigned)(chunk * 8));
-    if (mode == kRender) hipLaunchKernelGGL((k_raster<TW, TH, kRender>), grid, dim3(kWG), 0, st, bd, a);
-    else if (mode == kCost) hipLaunchKernelGGL((k_raster<TW, TH, kCost>), grid, dim3(kWG), 0, st, bd, a);
-    else if (mode == kIcp) hipLaunchKernelGGL((k_raster<TW, TH, kIcp>), grid, dim3(kWG), 0, st, bd, a);
-    else hipLaunchKernelGGL((k_raster<TW, TH, kGrad>), grid, dim3(kWG), 0, st, bd, a);
+    if (a.spill) {
+        if (mode == kRender) hipLaunchKernelGGL((k_raster<TW, TH, kRender, true>), grid, dim3(kWG), 0, st, bd, a);
+        else if (mode == kCost) hipLaunchKernelGGL((k_raster<TW, TH, kCost, true>), grid, dim3(kWG), 0, st, bd, a);
+        else if (mode == kIcp) hipLaunchKernelGGL((k_raster<TW, TH, kIcp, true>), grid, dim3(kWG), 0, st, bd, a);
+        else hipLaunchKernelGGL((k_raster<TW, TH, kGrad, true>), grid, dim3(kWG), 0, st, bd, a);
+    } else {
+        if (mode == kRender) hipLaunchKernelGGL((k_raster<TW, TH, kRender, false>), grid, dim3(kWG), 0, st, bd, a);
+        else if (mode == kCost) hipLaunchKernelGGL((k_raster<TW, TH, kCost, false>), grid, dim3(kWG), 0, st, bd, a);
+        else if (mode == kIcp) hipLaunchKernelGGL((k_raster<TW, TH, kIcp, false>), grid, dim3(kWG), 0, st, bd, a);
+        else hipLaunchKernelGGL((k_raster<TW, TH, kGrad, false>), grid, dim3(kWG), 0, st, bd, a);
+    }
     return hipGetLastError();
 }
 
@@ -1495,10 +1663,20 @@ hipError_t launch_vis_sort(hipStream_t st, const BatchDesc& bd, int32_t n_cluste
 
 hipError_t launch_bin(hipStream_t st, const BatchDesc& bd, const RasterArgs& a) {
     if (bd.n_items == 0 || a.n_clusters == 0) return hipSuccess;
-    if (bd.tile_w == 8 && bd.tile_h == 8) return launch_bin_t<8, 8>(st, bd, a);
-    if (bd.tile_w == 16 && bd.tile_h == 16) return launch_bin_t<16, 16>(st, bd, a);
-    if (bd.tile_w == 64 && bd.tile_h == 32) return launch_bin_t<64, 32>(st, bd, a);
-    return launch_bin_t<32, 32>(st, bd, a);
+    return a.spill_top ? launch_bin_shape<true>(st, bd, a) : launch_bin_shape<false>(st, bd, a);
+}
+
+hipError_t launch_overflow(hipStream_t st, const RasterArgs& a, int64_t n_records) {
+    if (n_records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_region_alloc, dim3((unsigned)((n_records + kWG - 1) / kWG)), dim3(kWG), 0, st, a,
+                       n_records);
+    if (a.spill_cap > 0 && a.pool_cap > 0) {
+        // enough workgroups to fill the device; each strides over its list
+        hipLaunchKernelGGL(k_region_fill, dim3(4096), dim3(kWG), 0, st, a);
+        const unsigned g = (unsigned)std::min<int64_t>((a.spill_cap + kWG - 1) / kWG, 8192);
+        hipLaunchKernelGGL(k_spill_scatter, dim3(g), dim3(kWG), 0, st, a, n_records);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_order(hipStream_t st, const BatchDesc& bd, const int32_t* bin_small, const int32_t* bin_big,
@@ -1517,7 +1695,7 @@ int resident_blocks() {
     static int cached = 0;
     if (!cached) {
         int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster<TW, TH, MODE>, kWG, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster<TW, TH, MODE, false>, kWG, 0) != hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();

@@ -33,6 +33,7 @@ ABI_SYMBOLS = [
     "rm_mesh_from_range", "rm_mesh_clusters_size", "rm_mesh_clusters", "rm_render_depth", "rm_align_cost",
     "rm_align_cost_grad", "rm_gn_step", "rm_adam_step", "rm_se3_retract", "rm_depth_downsample",
     "rm_depth_normals", "rm_vertex_normals", "rm_icp_cost_grad", "rm_table_cost_weighted", "rm_set_bin_cap",
+    "rm_set_bin_pool",
     "rm_align_cost_grad_noalloc", "rm_profile_read_binning",
 ]
 TABLE_WEIGHTS = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)   # Table I as printed: reproduces E_TABLE
@@ -89,6 +90,7 @@ def load_library(path: Path | str | None = None):
             "rm_autotune": [V, I32],
             "rm_set_schedule": [V, I32],
             "rm_set_bin_cap": [V, I32],
+            "rm_set_bin_pool": [V, I64],
             "rm_get_tile": [V, I32, I32, I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)],
             "rm_profile": [V, I32],
             "rm_profile_read": [V, ctypes.POINTER(I64), ctypes.POINTER(D)],
@@ -166,6 +168,11 @@ class Context:
     def set_bin_cap(self, cap: int):
         """rm_set_bin_cap: fixed tile-bin capacity in entries (0: adaptive)."""
         _check(self.lib.rm_set_bin_cap(self.handle, int(cap)), self.handle)
+
+    def set_bin_pool(self, entries: int):
+        """rm_set_bin_pool: overflow pool of the tile bins (-1 adaptive, 0 none,
+        > 0 fixed entries)."""
+        _check(self.lib.rm_set_bin_pool(self.handle, int(entries)), self.handle)
 
     def autotune(self, enable: bool = True):
         _check(self.lib.rm_autotune(self.handle, int(enable)), self.handle)

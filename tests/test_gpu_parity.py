@@ -499,12 +499,25 @@ def _records_close(o, base):
     np.testing.assert_allclose(o[:, 18:45], base[:, 18:45], rtol=1e-4, atol=1e-6 * np.abs(base[:, 18:45]).max())
 
 
-def test_bin_capacity_override_takes_the_overflow_path(rm):
+def _plans(text):
+    """(bin capacity, spill-list entries, region entries, bins that spill,
+    entries they spill, entries they hold in all) of each sizing pass in
+    RM_LOG output."""
+    import re
+    pat = re.compile(r"bin capacity (\d+) \(\d+ for large footprints; largest fills \d+ small, \d+ large\), "
+                     r"overflow list (\d+) and regions (\d+) entries \((\d+) bins spill (\d+) of (\d+) entries\)")
+    return [tuple(int(x) for x in m.groups()) for m in pat.finditer(text)]
+
+
+def test_bin_capacity_override_takes_the_overflow_path(rm, capfd, monkeypatch):
     """rm_set_bin_cap fixes the tile-bin capacity: at 1 entry every bin with
-    more than one triangle overflows and its tile is rasterized from every
-    visible cluster of its pose; at 16 and 256 entries, some do.  Records are
-    bit-identical to the adaptive capacity, eagerly and replayed from a
-    captured graph, and the adaptive capacity is restored afterwards."""
+    more than one triangle overflows, at 16 and 256 entries some do.  The
+    entries past a bin's capacity spill to the overflow regions (adaptive by
+    default), or, with no overflow or when a small fixed one is full, the
+    tile is rasterized from every visible cluster of its pose.  Records are
+    bit-identical to the adaptive capacity on every path, eagerly and
+    replayed from captured graphs, the sizing pass reports the overflow it
+    used, and the defaults are restored afterwards."""
     _say("bin capacity override")
     w = workload("kinect")
     dm = _dev_mesh(rm, oracle_map("kinect"))
@@ -514,33 +527,92 @@ def test_bin_capacity_override_takes_the_overflow_path(rm):
     ctx = rm.context()
     with pytest.raises(rm.RenderMapError):
         ctx.set_bin_cap(-1)
+    with pytest.raises(rm.RenderMapError):
+        ctx.set_bin_pool(-2)
+    monkeypatch.setenv("RM_LOG", "1")
     try:
         for cap in (1, 16, 256):
             ctx.set_bin_cap(cap)
-            o = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
-            np.testing.assert_array_equal(o, base)
+            for pool in (0, -1, 4096):
+                ctx.set_bin_pool(pool)
+                capfd.readouterr()
+                o = rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy()
+                plans = _plans(capfd.readouterr().err)
+                _say(f"cap {cap} pool {pool}: sizing passes {plans}")
+                np.testing.assert_array_equal(o, base)
+                assert plans and all(p[0] == cap for p in plans)
+                bc, lst, regs, nrec, spilled, filled = plans[-1]
+                assert nrec > 0 and spilled > 0 and filled >= spilled   # some bins overflow at these capacities
+                if pool == 0:
+                    assert lst == 0 and regs == 0
+                elif pool == -1:
+                    assert lst >= spilled and regs >= filled            # every overflowing bin has a region
+                else:
+                    assert lst == pool and regs == pool
+                # a second call of the shape (sized; asynchronous adaptation only)
+                np.testing.assert_array_equal(rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy(), base)
             rd = rm.render_depth(dm, w.cam, T[:2].contiguous())
             ctx.set_bin_cap(0)
             rb = rm.render_depth(dm, w.cam, T[:2].contiguous())
             ctx.set_bin_cap(cap)
             np.testing.assert_array_equal(rd["tri"].cpu().numpy(), rb["tri"].cpu().numpy())
         ctx.set_bin_cap(1)
-        out = torch.empty((16, rm.OUT_STRIDE), dtype=torch.float64, device=DEV)
-        rm.align_cost_grad(dm, scan, T, EPS, out=out)
-        torch.cuda.synchronize()
-        g = rm.Graph(DEV)
-        with g:
+        for pool in (-1, 0):
+            ctx.set_bin_pool(pool)
+            out = torch.empty((16, rm.OUT_STRIDE), dtype=torch.float64, device=DEV)
             rm.align_cost_grad(dm, scan, T, EPS, out=out)
-        for _ in range(3):
-            out.zero_()
-            g.replay()
-            junk = torch.randn(1000, device=DEV).sum()
             torch.cuda.synchronize()
-            np.testing.assert_array_equal(out.cpu().numpy(), base)
-            del junk
+            g = rm.Graph(DEV)
+            with g:
+                rm.align_cost_grad(dm, scan, T, EPS, out=out)
+            for _ in range(3):
+                out.zero_()
+                g.replay()
+                junk = torch.randn(1000, device=DEV).sum()
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(out.cpu().numpy(), base)
+                del junk
+            del g
     finally:
         ctx.set_bin_cap(0)
+        ctx.set_bin_pool(-1)
     np.testing.assert_array_equal(rm.align_cost_grad(dm, scan, T, EPS).cpu().numpy(), base)
+
+
+@pytest.mark.slow
+def test_uneven_stream_overflow_pool(rm, capfd, monkeypatch):
+    """The uneven stream of 32 scans (2,522 poses, 320x240 to 1280x960, 2.1M
+    triangles): the bin capacity its 712,110 (pose, tile) records can take in
+    the budget is far below its fullest bins, whose excess spills to overflow
+    regions.  Records equal those of the every-cluster path (no overflow) and
+    of an overflow too small for all of them, bit for bit."""
+    _say("uneven stream, overflow pool")
+    st = stream("uneven")
+    dms = _dev_mesh(rm, stream_map("uneven"))
+    scans = [rm.scan_image(torch.from_numpy(x.depth).to(DEV), st.z_min, st.z_max, cam=x.cam) for x in st.scans]
+    counts = [len(x.poses) for x in st.scans]
+    Ts = _T(np.concatenate([x.poses for x in st.scans]))
+    ctx = rm.context()
+    ctx.set_tile(64, 32)
+    monkeypatch.setenv("RM_LOG", "1")
+    try:
+        capfd.readouterr()
+        got = rm.align_cost_grad(dms, scans, Ts, EPS, poses_per_scan=counts).cpu().numpy()
+        plans = _plans(capfd.readouterr().err)
+        _say(f"sizing passes {plans}")
+        bc, lst, regs, nrec, spilled, filled = plans[-1]
+        assert nrec > 0 and lst >= spilled > 0 and regs >= filled
+        again = rm.align_cost_grad(dms, scans, Ts, EPS, poses_per_scan=counts).cpu().numpy()
+        np.testing.assert_array_equal(again, got)
+        ctx.set_bin_pool(filled // 3)
+        part = rm.align_cost_grad(dms, scans, Ts, EPS, poses_per_scan=counts).cpu().numpy()
+        ctx.set_bin_pool(0)
+        none = rm.align_cost_grad(dms, scans, Ts, EPS, poses_per_scan=counts).cpu().numpy()
+    finally:
+        ctx.set_bin_pool(-1)
+        ctx.set_tile(0, 0)
+    np.testing.assert_array_equal(part, got)
+    np.testing.assert_array_equal(none, got)
 
 
 @pytest.mark.slow
