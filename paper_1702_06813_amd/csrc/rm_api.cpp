@@ -51,7 +51,11 @@ struct rm_ctx {
     int64_t pool_mode = -1;
     int64_t list_want = 0;            // spill-list entries learned (adaptive)
     int64_t region_want = 0;          // overflow-region entries learned (adaptive)
-    bool pool_track = false;          // bin with the spilling kernel (it measures what overflow must hold)
+    // launch shapes (records, tile, triangles, poses) whose bins have outgrown
+    // a capacity that could not grow: their calls bin with the spilling kernel
+    // (which also measures what overflow must hold) and get overflow room
+    std::set<std::tuple<int64_t, int, int, int64_t, int>> track_shapes;
+    std::tuple<int64_t, int, int, int64_t, int> pending_shape;   // of the pending readback
     hipEvent_t bin_ev = nullptr;      // recorded after the readback of the largest bins
     bool bin_pending = false;
     bool pool_pending = false;        // the pending readback includes what the call spilled
@@ -285,9 +289,9 @@ void adapt_bin_cap(rm_ctx* ctx, int64_t n_records) {
     }
     if (ctx->bin_cap_fixed == 0) learn_bins(ctx, n_records, fs, fb);
     if (fs <= ctx->last_cap_s && fb <= ctx->last_cap_b) return;
-    // bins that would still overflow at the next call's capacity spill from then on
-    const int64_t cap = call_cap(ctx, n_records), cap_b = big_part(ctx, cap);
-    if ((fs > cap - cap_b || fb > cap_b) && ctx->pool_mode < 0) ctx->pool_track = true;
+    // bins that would still overflow at the capacity of their shape's next call spill from then on
+    const int64_t cap = call_cap(ctx, std::get<0>(ctx->pending_shape)), cap_b = big_part(ctx, cap);
+    if ((fs > cap - cap_b || fb > cap_b) && ctx->pool_mode < 0) ctx->track_shapes.insert(ctx->pending_shape);
 }
 
 // Starts the timing of one launch of kernel k (0 rasterizer, 1 binning) when
@@ -346,10 +350,11 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         cap = call_cap(ctx, R);
         // overflow: spill-list entries (12 bytes) and region entries (4
         // bytes), as learned, scaled down to what the budget leaves beside the bins
+        const bool shape_track = pool_adaptive && ctx->track_shapes.count(shape) > 0;
         int64_t spill_cap = 0, pool_cap = 0;
         if (!arena.fixed && ctx->pool_mode > 0) {
             spill_cap = pool_cap = ctx->pool_mode;
-        } else if (pool_adaptive) {
+        } else if (shape_track) {
             const double room = (double)std::max<int64_t>(0, ctx->bin_budget - R * cap * 4);
             const double want = 12.0 * (double)ctx->list_want + 4.0 * (double)ctx->region_want;
             const double f = want > room ? room / want : 1.0;
@@ -358,7 +363,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         }
         spill_cap = std::min<int64_t>(spill_cap, 0xfffffffell);
         // the spilling kernel also measures what overflow must hold: always in a sizing pass
-        const bool track = !arena.fixed && (check || spill_cap > 0 || (ctx->pool_track && ctx->pool_mode != 0));
+        const bool track = !arena.fixed && (check || ctx->pool_mode > 0 || shape_track);
         Carve cv;
         // vis_count, vis_tris, bin_max[2], bin_fill[2], bin fills, order histogram and cursors, queue
         const int64_t n_cnt = 2 * (int64_t)P + 4 + 2 * R + 65;
@@ -496,12 +501,12 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
                 if (log)
                     fprintf(stderr, "[rendermap] bins grown to %lld entries (%lld large); binning again\n",
                             (long long)c2, (long long)b2);
-                if (pool_adaptive && (fs > c2 - b2 || fb > b2)) ctx->pool_track = true;
+                if (pool_adaptive && (fs > c2 - b2 || fb > b2)) ctx->track_shapes.insert(shape);
                 continue;
             }
         }
         // the bins cannot grow: what outgrows them spills
-        if (pool_adaptive) ctx->pool_track = true;
+        if (pool_adaptive) ctx->track_shapes.insert(shape);
         const bool placed = spilled <= a.spill_cap && filled <= a.pool_cap;
         if (placed || !pool_adaptive) {
             if (!placed && log)
@@ -545,6 +550,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         ctx->pool_pending = a.spill_top != nullptr;
         ctx->last_cap_s = (int32_t)(cap - cap_b);
         ctx->last_cap_b = (int32_t)cap_b;
+        ctx->pending_shape = shape;
     }
     return RM_OK;
 }
@@ -765,6 +771,7 @@ int rm_set_bin_cap(rm_ctx* ctx, int32_t cap) {
     if (cap < 0 || cap > (1 << 24)) return fail(ctx, RM_ERR_INVALID_ARG, "bin capacity %d outside 0..2^24", cap);
     ctx->bin_cap_fixed = cap;
     ctx->bin_checked.clear();         // the next call of each shape sizes its bins again
+    ctx->track_shapes.clear();
     return RM_OK;
 }
 
@@ -775,6 +782,7 @@ int rm_set_bin_pool(rm_ctx* ctx, int64_t entries) {
         return fail(ctx, RM_ERR_INVALID_ARG, "overflow pool of %lld entries outside -1..2^40", (long long)entries);
     ctx->pool_mode = entries;
     ctx->bin_checked.clear();
+    ctx->track_shapes.clear();
     return RM_OK;
 }
 
