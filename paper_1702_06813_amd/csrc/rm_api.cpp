@@ -361,7 +361,8 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
             spill_cap = (int64_t)((double)ctx->list_want * f);
             pool_cap = (int64_t)((double)ctx->region_want * f);
         }
-        spill_cap = std::min<int64_t>(spill_cap, 0xfffffffell);
+        // (whole segments; the list stays below 2^32 - 1 entries)
+        spill_cap = std::min<int64_t>(spill_cap, 0xfffffffell) / kSpillLists * kSpillLists;
         // the spilling kernel also measures what overflow must hold: always in a sizing pass
         const bool track = !arena.fixed && (check || ctx->pool_mode > 0 || shape_track);
         Carve cv;
@@ -373,9 +374,10 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         const size_t o_visz = cv.take<float>((int64_t)P * C);
         const size_t o_rec = cv.take<float>(mode == kRender ? 1 : R * kRecFields);
         const size_t o_cb = cv.take<char>(mesh->clusters ? 1 : rm_mesh_clusters_size(mesh->n_tris));
-        // spill counters [5] (u64) and lost flags [R], zeroed; region offsets; spilled
+        // spill counters (u64) and lost flags [R], zeroed; region offsets; spilled
         // records; spill list; regions
-        const int64_t n_sz = track ? 10 + R : 0;
+        const int64_t n_cnt64 = kSpillTops + 2 * kSpillLists;
+        const int64_t n_sz = track ? 2 * n_cnt64 + R : 0;
         const size_t o_sz = track ? cv.take<int32_t>(n_sz) : 0;
         const size_t o_poff = track ? cv.take<int64_t>(R) : 0;
         const size_t o_srec = track ? cv.take<int32_t>(R) : 0;
@@ -441,7 +443,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         a.bin_cap = (int32_t)cap;
         a.bin_big_cap = (int32_t)cap_b;
         a.spill_top = track ? reinterpret_cast<unsigned long long*>(at(o_sz)) : nullptr;
-        a.spill_lost = track ? reinterpret_cast<int32_t*>(at(o_sz)) + 10 : nullptr;
+        a.spill_lost = track ? reinterpret_cast<int32_t*>(at(o_sz)) + 2 * n_cnt64 : nullptr;
         a.spill_recs = track ? reinterpret_cast<int32_t*>(at(o_srec)) : nullptr;
         a.pool_off = track ? reinterpret_cast<int64_t*>(at(o_poff)) : nullptr;
         // (a list without regions would place nothing: keep neither)
@@ -488,8 +490,8 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
             fprintf(stderr,
                     "[rendermap] plan: %d scans, %d poses, %lld triangles (%lld clusters), tile %dx%d, %lld tile "
                     "records, %s schedule, bin capacity %lld (%lld for large footprints; largest fills %lld "
-                    "small, %lld large), overflow list %lld and regions %lld entries (%lld bins spill %lld of "
-                    "%lld entries), %zu bytes of scratch\n",
+                    "small, %lld large), overflow list %lld and regions %lld entries (%lld bins spill; they need "
+                    "%lld list and %lld region entries), %zu bytes of scratch\n",
                     bd.n_scans, P, (long long)mesh->n_tris, (long long)C, tw, th, (long long)R,
                     persistent ? "persistent longest-first" : "one workgroup per item", (long long)cap,
                     (long long)cap_b, (long long)fs, (long long)fb, (long long)a.spill_cap, (long long)a.pool_cap,

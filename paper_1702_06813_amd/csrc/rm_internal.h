@@ -13,6 +13,8 @@ constexpr int kClusterTris = RM_CLUSTER_TRIS;
 constexpr int kQuadBlock = 8;            // meshify emits 8x8 blocks of quads
 constexpr int kRecFields = 41;           // per-(pose, tile) partial record, 4-byte fields
 constexpr int kSnapLimit = 1 << 29;      // |snapped coordinate| must stay below this
+constexpr int kSpillLists = 64;           // spill-list segments (each with its own counter)
+constexpr int kSpillTops = 8;             // spill counters before the segments' fills
 constexpr int kBinTable = 2048;          // tiles of a cluster rectangle binned per LDS pass (taller
                                          // rectangles are binned in bands of rows)
 constexpr int kMaxTileGrid = 256;        // tiles per image row and column (8-bit rectangle fields)
@@ -80,9 +82,11 @@ struct RasterArgs {
     // out of room for it (spill_lost) or the regions did.
     uint3* spill;                // [spill_cap]
     int64_t spill_cap;           // list entries, < 2^32 - 1
-    unsigned long long* spill_top;  // device [5], zeroed: list entries asked for, region cursor, records
-                                    // spilled, spill_cap minus the start of the first list range that
-                                    // crossed the end, region entries asked for
+    unsigned long long* spill_top;  // device [kSpillTops + 2 kSpillLists], zeroed: list entries asked for
+                                    // (kSpillLists times the fullest segment), region cursor, records
+                                    // spilled, unused, region entries asked for, unused [3]; then the
+                                    // fill of each list segment, then each segment's length minus the
+                                    // start of its first range that crossed the segment's end
     int32_t* spill_lost;         // [n_records], zeroed
     int32_t* spill_recs;         // [n_records] records that spilled, -1 where without a region
     uint32_t* pool;              // [pool_cap] overflow regions

@@ -758,13 +758,17 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
                 // one range of the list for the band; if it does not fit,
                 // the records that spilled here are lost
                 if (threadIdx.x == 0 && band_spill) {
-                    const unsigned long long sp = atomicAdd(a.spill_top, (unsigned long long)band_spill);
-                    const unsigned long long cap_l = (unsigned long long)a.spill_cap;
-                    band_base = sp;
-                    band_spill = sp + band_spill <= cap_l ? 1u : 2u;
-                    // a range that crosses the end of the list leaves its part
-                    // below the end unwritten: the list is valid below its start
-                    if (sp < cap_l && band_spill == 2u) atomicMax(a.spill_top + 3, cap_l - sp);
+                    // the list is cut into kSpillLists segments with counters of
+                    // their own, so that bands do not all contend for one address
+                    const unsigned seg = (blockIdx.y * 131u + blockIdx.x) % kSpillLists;
+                    const unsigned long long len = (unsigned long long)a.spill_cap / kSpillLists;
+                    const unsigned long long sp = atomicAdd(a.spill_top + kSpillTops + seg, (unsigned long long)band_spill);
+                    band_base = seg * len + sp;
+                    band_spill = sp + band_spill <= len ? 1u : 2u;
+                    // a range that crosses the end of its segment leaves its part
+                    // below the end unwritten: the segment is valid below its start
+                    if (sp < len && band_spill == 2u)
+                        atomicMax(a.spill_top + kSpillTops + kSpillLists + seg, len - sp);
                 }
                 __syncthreads();
                 if (band_spill == 2u)
@@ -829,6 +833,13 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
 // they lie.
 __global__ void __launch_bounds__(kWG) k_region_alloc(RasterArgs a, int64_t n) {
     const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (r == 0) {
+        // what the list must hold: its segments are filled alike, so as many
+        // times the fullest segment as there are segments
+        unsigned long long m = 0;
+        for (int s = 0; s < kSpillLists; ++s) m = max(m, a.spill_top[kSpillTops + s]);
+        a.spill_top[0] = m * kSpillLists;
+    }
     if (r >= n) return;
     const int ns = a.bin_small[r], nb = a.bin_big[r];
     int64_t off = -1;
@@ -870,14 +881,16 @@ __global__ void __launch_bounds__(kWG) k_region_fill(RasterArgs a) {
 }
 
 // Places each spilled entry at its slot in its record's region (entries of
-// records without a region stay out).  Every entry below the start of the
-// first range that crossed the end of the list was written by this call.
+// records without a region stay out); blockIdx.y is the list segment.  Every
+// entry of a segment below the start of its first range that crossed the
+// segment's end was written by this call.
 __global__ void __launch_bounds__(kWG) k_spill_scatter(RasterArgs a, int64_t n_records) {
-    const unsigned long long cap_l = (unsigned long long)a.spill_cap;
-    const unsigned long long n = min(a.spill_top[0], cap_l - a.spill_top[3]);
+    const unsigned seg = blockIdx.y;
+    const unsigned long long len = (unsigned long long)a.spill_cap / kSpillLists;
+    const unsigned long long n = min(a.spill_top[kSpillTops + seg], len - a.spill_top[kSpillTops + kSpillLists + seg]);
     for (unsigned long long j = (unsigned long long)blockIdx.x * kWG + threadIdx.x; j < n;
          j += (unsigned long long)gridDim.x * kWG) {
-        const uint3 e = a.spill[j];
+        const uint3 e = a.spill[seg * len + j];
         if ((int64_t)e.y >= n_records) continue;      // (never: each entry names a record of the call)
         const int64_t off = a.pool_off[e.y];
         if (off < 0) continue;
@@ -1673,8 +1686,9 @@ hipError_t launch_overflow(hipStream_t st, const RasterArgs& a, int64_t n_record
     if (a.spill_cap > 0 && a.pool_cap > 0) {
         // enough workgroups to fill the device; each strides over its list
         hipLaunchKernelGGL(k_region_fill, dim3(4096), dim3(kWG), 0, st, a);
-        const unsigned g = (unsigned)std::min<int64_t>((a.spill_cap + kWG - 1) / kWG, 8192);
-        hipLaunchKernelGGL(k_spill_scatter, dim3(g), dim3(kWG), 0, st, a, n_records);
+        const int64_t len = a.spill_cap / kSpillLists;
+        const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((len + kWG - 1) / kWG, 128));
+        hipLaunchKernelGGL(k_spill_scatter, dim3(g, kSpillLists), dim3(kWG), 0, st, a, n_records);
     }
     return hipGetLastError();
 }
