@@ -312,6 +312,26 @@ int prof_begin(rm_ctx* ctx, int k, bool fixed, hipEvent_t* stop) {
     return RM_OK;
 }
 
+// Overflow room of a call with n_records bins of capacity cap: the fixed
+// size, or for a shape that tracks overflow what was learned, scaled down
+// to what the budget leaves beside the bins (list entries 12 bytes, region
+// entries 4), the list in whole segments below 2^32 - 1 entries.
+void overflow_caps(const rm_ctx* ctx, int64_t n_records, int64_t cap, bool fixed_arena, bool track,
+                   int64_t* spill_cap, int64_t* pool_cap) {
+    int64_t sc = 0, pc = 0;
+    if (!fixed_arena && ctx->pool_mode > 0) {
+        sc = pc = ctx->pool_mode;
+    } else if (!fixed_arena && ctx->pool_mode < 0 && track) {
+        const double room = (double)std::max<int64_t>(0, ctx->bin_budget - n_records * cap * 4);
+        const double want = 12.0 * (double)ctx->list_want + 4.0 * (double)ctx->region_want;
+        const double f = want > room ? room / want : 1.0;
+        sc = (int64_t)((double)ctx->list_want * f);
+        pc = (int64_t)((double)ctx->region_want * f);
+    }
+    *spill_cap = std::min<int64_t>(sc, 0xfffffffell) / kSpillLists * kSpillLists;
+    *pool_cap = pc;
+}
+
 // One scoring pass: cull, near-to-far cluster order, bin, rasterize (+ fused
 // comparison), reduce.
 int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, int mode, const double* T_wc,
@@ -352,17 +372,7 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
         // bytes), as learned, scaled down to what the budget leaves beside the bins
         const bool shape_track = pool_adaptive && ctx->track_shapes.count(shape) > 0;
         int64_t spill_cap = 0, pool_cap = 0;
-        if (!arena.fixed && ctx->pool_mode > 0) {
-            spill_cap = pool_cap = ctx->pool_mode;
-        } else if (shape_track) {
-            const double room = (double)std::max<int64_t>(0, ctx->bin_budget - R * cap * 4);
-            const double want = 12.0 * (double)ctx->list_want + 4.0 * (double)ctx->region_want;
-            const double f = want > room ? room / want : 1.0;
-            spill_cap = (int64_t)((double)ctx->list_want * f);
-            pool_cap = (int64_t)((double)ctx->region_want * f);
-        }
-        // (whole segments; the list stays below 2^32 - 1 entries)
-        spill_cap = std::min<int64_t>(spill_cap, 0xfffffffell) / kSpillLists * kSpillLists;
+        overflow_caps(ctx, R, cap, arena.fixed != nullptr, shape_track, &spill_cap, &pool_cap);
         // the spilling kernel also measures what overflow must hold: always in a sizing pass
         const bool track = !arena.fixed && (check || ctx->pool_mode > 0 || shape_track);
         Carve cv;
@@ -515,17 +525,17 @@ int run_pass(rm_ctx* ctx, const rm_mesh* mesh, BatchDesc& bd, int tw, int th, in
                 fprintf(stderr, "[rendermap] bins whose overflow does not fit take the every-cluster path\n");
             break;
         }
-        const int64_t lw = std::max(ctx->list_want, pool_margin(spilled));
-        const int64_t rw = std::max(ctx->region_want, pool_margin(filled));
-        if (lw == ctx->list_want && rw == ctx->region_want) {
+        ctx->list_want = std::max(ctx->list_want, pool_margin(spilled));
+        ctx->region_want = std::max(ctx->region_want, pool_margin(filled));
+        int64_t next_spill = 0, next_pool = 0;
+        overflow_caps(ctx, R, cap, false, true, &next_spill, &next_pool);
+        if (next_spill <= a.spill_cap && next_pool <= a.pool_cap) {
             if (log) fprintf(stderr, "[rendermap] the budget leaves the overflow no more room\n");
             break;
         }
-        ctx->list_want = lw;
-        ctx->region_want = rw;
         if (log)
             fprintf(stderr, "[rendermap] overflow sized to %lld list and %lld region entries; binning again\n",
-                    (long long)lw, (long long)rw);
+                    (long long)next_spill, (long long)next_pool);
     }
     hipEvent_t pe1;
     {

@@ -153,7 +153,7 @@ __device__ __forceinline__ float snap_min(const float* rmin, int y, int x0, int 
 // centres of their bounding box inside the tile (int32 edge functions).
 __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const Tile& tl, const float* rmin,
                                              const int X[3], const int Y[3], int px0, int px1, int py0, int py1,
-                                             const WPlane& pl, double cx, double cy, float w_far, uint32_t id) {
+                                             const WPlane& pl, double cx, double cy, uint32_t id) {
     int E[3], sx[3], sy[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -173,11 +173,13 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
         // visible in this row: every atomic below would leave the keys unchanged
         const double wn = fmax(wrow, fma(pl.a, (double)(px1 - px0), wrow));
         const int xend = wn * kOccMargin < (double)snap_min(rmin, y - tl.y0, px0 - tl.x0, px1 - tl.x0) ? px0 - 1 : px1;
-        for (int x = px0; x <= xend; ++x) {
+        // (the loop runs on the key address; the far plane is applied at
+        // the resolve, see there)
+        for (uint64_t *k = row + px0, *kend = row + xend; k <= kend; ++k) {
             {   // branch-free: an uncovered pixel offers the empty key, which changes nothing
                 const float wf = (float)w;
-                const bool cov = ((e0 | e1 | e2) >= 0) & (wf >= w_far);
-                atomicMin((unsigned long long*)(row + x), cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
+                const bool cov = (e0 | e1 | e2) >= 0;
+                atomicMin((unsigned long long*)k, cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
             }
             e0 += sx[0]; e1 += sx[1]; e2 += sx[2];
             w += pl.a;
@@ -215,8 +217,7 @@ struct BigQueue {
 __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Tile& tl, const float* rmin,
                                             const int X[3], const int Y[3], const double m[3], double pa, double pb,
                                             double pe,
-                                            uint32_t id, int bx0, int bx1, int r0, int r1, double cx, double cy,
-                                            float w_far) {
+                                            uint32_t id, int bx0, int bx1, int r0, int r1, double cx, double cy) {
     int64_t E[3];
     int dx[3], dy[3];
     double xc[3];
@@ -247,17 +248,20 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
         const int xb = min(bx1, (int)floor(fmax(hi, (double)bx0 - 1.0) + 1e-6));
         double w = fma(pa, (double)(xa - bx0), wrow);
         if (!empty && xa <= xb && fmax(w, fma(pa, (double)(xb - xa), w)) * kOccMargin >= (double)snap_min(rmin, r, xa, xb)) {
-            int64_t e0 = E[0] - 256 * (int64_t)dy[0] * (xa - bx0);
-            int64_t e1 = E[1] - 256 * (int64_t)dy[1] * (xa - bx0);
-            int64_t e2 = E[2] - 256 * (int64_t)dy[2] * (xa - bx0);
+            // The bracket's crossings are exact to far below a pixel, so a
+            // pixel centre one pixel or more inside it is covered: only its
+            // end pixels take the exact int64 edge test, and an end that
+            // fails it is left out of the span.
+            auto inside = [&](int x) {
+                const int64_t o = 256 * (int64_t)(x - bx0);
+                return ((E[0] - o * dy[0]) | (E[1] - o * dy[1]) | (E[2] - o * dy[2])) >= 0;
+            };
+            const bool in_a = inside(xa), in_b = inside(xb);
+            if (!in_a) w += pa;                // the span's first pixel, accumulated as before
             uint64_t* row = keys + r * tile_w;
-            for (int x = xa; x <= xb; ++x) {
-                {
-                    const float wf = (float)w;
-                    const bool cov = ((e0 | e1 | e2) >= 0) & (wf >= w_far);
-                    atomicMin((unsigned long long*)(row + x), cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
-                }
-                e0 -= 256 * (int64_t)dy[0]; e1 -= 256 * (int64_t)dy[1]; e2 -= 256 * (int64_t)dy[2];
+            const uint64_t lo_id = id;
+            for (uint64_t *k = row + xa + (in_a ? 0 : 1), *kend = row + xb - (in_b ? 0 : 1); k <= kend; ++k) {
+                atomicMin((unsigned long long*)k, pack_key((float)w, 0) | lo_id);
                 w += pa;
             }
         }
@@ -269,7 +273,7 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
 
 template <int TW, int TH>
 __device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const Tile& tl, const float* rmin,
-                                             double cx, double cy, float w_far) {
+                                             double cx, double cy) {
     const int nj = q.njobs;
     for (int j = threadIdx.x; j < nj; j += kWG) {
         const int rec = q.job[j];
@@ -281,7 +285,7 @@ __device__ __forceinline__ void raster_queue(uint64_t* keys, BigQueue& q, const 
         const int Y[3] = {q.Y[0][b], q.Y[1][b], q.Y[2][b]};
         const double m[3] = {q.m[0][b], q.m[1][b], q.m[2][b]};
         raster_rows(keys, TW, tl, rmin, X, Y, m, q.pa[b], q.pb[b], q.pe[b], q.id[b], (int)(box & 0xff),
-                    (int)((box >> 8) & 0xff), r0, r1, cx, cy, w_far);
+                    (int)((box >> 8) & 0xff), r0, r1, cx, cy);
     }
 }
 
@@ -296,7 +300,7 @@ struct Queues {
 };
 
 __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const float* rmin, const Tile& tl,
-                                         const CamF& cam, float3 A, float3 B, float3 C, const WPlane& pl, float w_far,
+                                         const CamF& cam, float3 A, float3 B, float3 C, const WPlane& pl,
                                          uint32_t id) {
     int X[3], Y[3];
     if (!snap(cam, A, X[0], Y[0]) || !snap(cam, B, X[1], Y[1]) || !snap(cam, C, X[2], Y[2])) return;
@@ -316,7 +320,7 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     const uint32_t box = (uint32_t)(px0 - tl.x0) | ((uint32_t)(px1 - tl.x0) << 8) | ((uint32_t)(py0 - tl.y0) << 16) |
                          ((uint32_t)(py1 - tl.y0) << 24);
     if (boxpx <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
-        raster_small(keys, tile_w, tl, rmin, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, w_far, id);
+        raster_small(keys, tile_w, tl, rmin, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, id);
         return;
     }
     int Xr[3], Yr[3];
@@ -332,7 +336,7 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     const int k = atomicAdd(&Q.big.n, 1);
     if (k >= kQCap) {                          // queue full: this thread walks the rows itself
         raster_rows(keys, tile_w, tl, rmin, Xr, Yr, m, pl.a, pl.b, pl.e, id, px0 - tl.x0, px1 - tl.x0, py0 - tl.y0,
-                    py1 - tl.y0, (double)cam.cx, (double)cam.cy, w_far);
+                    py1 - tl.y0, (double)cam.cx, (double)cam.cy);
         return;
     }
 #pragma unroll
@@ -380,7 +384,7 @@ __device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, int
 // at most two sub-triangles (same id), setup and rasterization.
 template <int MODE>
 __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queues& q, const float* rmin,
-                                                const Tile& tl, const CamF& cam, double ifx, double ify, float w_far,
+                                                const Tile& tl, const CamF& cam, double ifx, double ify,
                                                 const PoseF& P, const TriIn& in) {
     const float x0 = in.v[0], y0 = in.v[1], z0 = in.v[2];
     const float3 V0 = cam_contract(P, x0, y0, z0);
@@ -439,7 +443,7 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
 #pragma unroll 1
     for (int sub = 0; sub < nsub; ++sub) {
         const float3 A = sub ? A1 : A0, B = sub ? B1 : B0, C = sub ? C1 : C0;
-        emit_tri(keys, tile_w, q, rmin, tl, cam, A, B, C, pl, w_far, id);
+        emit_tri(keys, tile_w, q, rmin, tl, cam, A, B, C, pl, id);
     }
 }
 
@@ -1056,9 +1060,9 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         load_indices(a.tri, a.vmax, t2, I2);
         t3 = entry(r + 3);
         __syncthreads();
-        if (cur.t >= 0) raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, w_far, P, cur);
+        if (cur.t >= 0) raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, P, cur);
         __syncthreads();
-        if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy, w_far);
+        if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy);
         __syncthreads();
         // row and tile snapshot for the next round (w >= 0, so its bits order
         // like its value).  Pixel p = tid + k kWG lies in row p / TW, so the
@@ -1108,7 +1112,11 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         const int x = tl.x0 + p % TW, y = tl.y0 + p / TW;
         if (x > tl.x1 || y > tl.y1) continue;
         const uint64_t key = keys[(y - tl.y0) * TW + (x - tl.x0)];
-        const bool hit = key != kEmptyKey;
+        // The rasterizers offer fragments beyond the far plane too (w below
+        // w_far); such a fragment is farther than any valid one, so it is
+        // the pixel's key only where no valid fragment exists, and a key
+        // beyond the far plane (or the empty key, w = 0) is no hit.
+        const bool hit = __uint_as_float(~(uint32_t)(key >> 32)) >= w_far;
         const uint32_t id = (uint32_t)key;
         const float z = hit ? 1.0f / __uint_as_float(~(uint32_t)(key >> 32)) : __int_as_float(0x7fc00000);
         const int64_t pix = (int64_t)y * cam.W + x;
