@@ -72,10 +72,12 @@ __device__ __forceinline__ bool snap(const CamF& c, float3 P, int& X, int& Y) {
 }
 
 __device__ __forceinline__ uint64_t pack_key(float w, uint32_t id) {
-    // nearer surface = larger w = 1/z = smaller key; equal depths: lower id wins
-    return ((uint64_t)(~__float_as_uint(w)) << 32) | (uint64_t)id;
+    // resolved by atomic maximum: nearer surface = larger w = 1/z = larger
+    // key (w >= 0, so its bits order like its value); equal depths: the
+    // lower id has the larger complement and wins
+    return ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~id);
 }
-constexpr uint64_t kEmptyKey = ~0ull;
+constexpr uint64_t kEmptyKey = 0ull;       // w = 0: behind everything
 
 // ------------------------------------------------------------------ tile rasterization
 
@@ -179,7 +181,7 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
             {   // branch-free: an uncovered pixel offers the empty key, which changes nothing
                 const float wf = (float)w;
                 const bool cov = (e0 | e1 | e2) >= 0;
-                atomicMin((unsigned long long*)k, cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
+                atomicMax((unsigned long long*)k, cov ? (unsigned long long)pack_key(wf, id) : kEmptyKey);
             }
             e0 += sx[0]; e1 += sx[1]; e2 += sx[2];
             w += pl.a;
@@ -259,9 +261,8 @@ __device__ __forceinline__ void raster_rows(uint64_t* keys, int tile_w, const Ti
             const bool in_a = inside(xa), in_b = inside(xb);
             if (!in_a) w += pa;                // the span's first pixel, accumulated as before
             uint64_t* row = keys + r * tile_w;
-            const uint64_t lo_id = id;
             for (uint64_t *k = row + xa + (in_a ? 0 : 1), *kend = row + xb - (in_b ? 0 : 1); k <= kend; ++k) {
-                atomicMin((unsigned long long*)k, pack_key((float)w, 0) | lo_id);
+                atomicMax((unsigned long long*)k, pack_key((float)w, id));
                 w += pa;
             }
         }
@@ -1074,7 +1075,7 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
             float* snap = q.rowmin[cb ^ 1];
             uint32_t tmin = 0x7f800000u;
             for (int p = tid; p < TW * TH; p += kWG) {
-                const uint32_t wb = group_min<kG>(~(uint32_t)(keys[p] >> 32));
+                const uint32_t wb = group_min<kG>((uint32_t)(keys[p] >> 32));
                 if ((lane & (kG - 1)) == 0) snap[(p / TW) * kSegs + (p % TW) / kSeg] = __uint_as_float(wb);
                 tmin = min(tmin, wb);
             }
@@ -1116,9 +1117,9 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         // w_far); such a fragment is farther than any valid one, so it is
         // the pixel's key only where no valid fragment exists, and a key
         // beyond the far plane (or the empty key, w = 0) is no hit.
-        const bool hit = __uint_as_float(~(uint32_t)(key >> 32)) >= w_far;
-        const uint32_t id = (uint32_t)key;
-        const float z = hit ? 1.0f / __uint_as_float(~(uint32_t)(key >> 32)) : __int_as_float(0x7fc00000);
+        const bool hit = __uint_as_float((uint32_t)(key >> 32)) >= w_far;
+        const uint32_t id = ~(uint32_t)key;
+        const float z = hit ? 1.0f / __uint_as_float((uint32_t)(key >> 32)) : __int_as_float(0x7fc00000);
         const int64_t pix = (int64_t)y * cam.W + x;
         if (MODE == kRender) {
             const int64_t o = (int64_t)it.pose * img + pix;
