@@ -671,7 +671,10 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
         const int ls = sw <= 1 ? 0 : 32 - __clz(sw - 1);
         const bool masked = (sh << ls) <= 64;
         const bool test_tiles = nspan > 2 && fabsf(area2) > 1e-3f;
-        const FootEdges g = foot_edges<TW, TH>(f, area2, (float)cam.W, (float)cam.H);
+        // (the edge functions only where the tile test runs: a wave whose
+        // footprints all span at most two tiles skips them)
+        FootEdges g = {};
+        if (test_tiles) g = foot_edges<TW, TH>(f, area2, (float)cam.W, (float)cam.H);
         uint64_t hits = 0;
         if (nspan > 0 && masked) {
             if (!test_tiles) {
@@ -705,8 +708,8 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
                 }
             } else {
                 for (int r = r0; r <= r1; ++r) {
-                    float k[4];
-                    edges_row(g, (float)((ty0 + r) * TH), k);
+                    float k[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (test_tiles) edges_row(g, (float)((ty0 + r) * TH), k);
                     for (int c = 0; c < sw; ++c)
                         if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW)))
                             atomicAdd(&tcnt[(ty0 + r - by0) * rw + (tx0 + c - rx0)], inc);
@@ -813,8 +816,8 @@ __global__ void __launch_bounds__(kWG) k_bin(BatchDesc bd, RasterArgs a, int32_t
                 }
             } else {
                 for (int r = r0; r <= r1; ++r) {
-                    float k[4];
-                    edges_row(g, (float)((ty0 + r) * TH), k);
+                    float k[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (test_tiles) edges_row(g, (float)((ty0 + r) * TH), k);
                     for (int c = 0; c < sw; ++c)
                         if (!test_tiles || edges_hit(g, k, (float)((tx0 + c) * TW))) put(tx0 + c, ty0 + r);
                 }
