@@ -129,7 +129,8 @@ int ensure_scratch(rm_ctx* ctx, size_t bytes) {
     }
     ctx->scratch = nullptr;
     ctx->scratch_size = 0;
-    const size_t sz = std::max(bytes + bytes / 4, (size_t)1 << 20);
+    // a quarter more for later calls that need a little more, at most 2 GiB
+    const size_t sz = std::max(bytes + std::min(bytes / 4, (size_t)2 << 30), (size_t)1 << 20);
     if (hipMalloc(&ctx->scratch, sz) != hipSuccess) {
         ctx->scratch = nullptr;
         (void)hipGetLastError();
