@@ -593,7 +593,6 @@ __device__ __forceinline__ int pose_scan(const BatchDesc& bd, int pose) {
 // global atomic); a band whose range does not fit marks its spilling
 // records lost instead.
 constexpr float kBigFootprint = 100.0f;    // bounding box area widened by 2 px per side, px
-constexpr uint32_t kNoSpill = 0xffffffffu; // marks a tile class of the band that did not spill
 constexpr uint32_t kBigSlot = 0x80000000u; // slot code of a large entry in the spill list
 
 // (six workgroups per CU: the plain variant fits them anyway; the spilling
@@ -625,6 +624,7 @@ __global__ void __launch_bounds__(kWG, 6) k_bin(BatchDesc bd, RasterArgs a, int3
     const int64_t rec0 = sd.rec_off + (int64_t)pl * ntile;
     const uint32_t cap = (uint32_t)a.bin_cap;
     const uint32_t cap_b = (uint32_t)a.bin_big_cap, cap_s = cap - cap_b;
+    int fs = 0, fb = 0;                        // largest fills this thread reserved (for bin_fill)
     for (int k = blockIdx.x; k < nvis; k += gridDim.x) {
         const uint2 e = a.vis[(int64_t)pose * a.n_clusters + k];
         const int rx0 = e.y & 0xff, rx1 = (e.y >> 8) & 0xff, ry0 = (e.y >> 16) & 0xff, ry1 = e.y >> 24;
@@ -719,8 +719,8 @@ __global__ void __launch_bounds__(kWG, 6) k_bin(BatchDesc bd, RasterArgs a, int3
             }
             if (SPILL && threadIdx.x == 0) band_spill = 0;
             __syncthreads();
-            int fs = 0, fb = 0;                    // largest fills this thread reserved
-            for (int i = threadIdx.x; i < nb; i += kWG) {
+            uint32_t spilled = 0;                  // bit j: tile threadIdx.x + j kWG reserved list space
+            for (int i = threadIdx.x, j = 0; i < nb; i += kWG, ++j) {
                 const uint32_t n = tcnt[i];
                 if (n) {
                     const int tile = (by0 + i / rw) * sd.tiles_x + rx0 + i % rw;
@@ -729,38 +729,21 @@ __global__ void __launch_bounds__(kWG, 6) k_bin(BatchDesc bd, RasterArgs a, int3
                         const uint32_t s0 = (uint32_t)atomicAdd(a.bin_small + rec, (int)(n & 0xffffu));
                         tbs[i] = s0;
                         fs = max(fs, (int)(s0 + (n & 0xffffu)));
-                        if (SPILL) {
-                            const uint32_t e = s0 + (n & 0xffffu);
-                            tss[i] = e > cap_s ? atomicAdd(&band_spill, e - max(s0, cap_s)) : kNoSpill;
+                        if (SPILL && s0 + (n & 0xffffu) > cap_s) {
+                            tss[i] = atomicAdd(&band_spill, s0 + (n & 0xffffu) - max(s0, cap_s));
+                            spilled |= 1u << j;
                         }
-                    } else if (SPILL) {
-                        tss[i] = kNoSpill;
                     }
                     if (n >> 16) {
                         const uint32_t b0 = (uint32_t)atomicAdd(a.bin_big + rec, (int)(n >> 16));
                         tbb[i] = b0;
                         fb = max(fb, (int)(b0 + (n >> 16)));
-                        if (SPILL) {
-                            const uint32_t e = b0 + (n >> 16);
-                            tsb[i] = e > cap_b ? atomicAdd(&band_spill, e - max(b0, cap_b)) : kNoSpill;
+                        if (SPILL && b0 + (n >> 16) > cap_b) {
+                            tsb[i] = atomicAdd(&band_spill, b0 + (n >> 16) - max(b0, cap_b));
+                            spilled |= 1u << j;
                         }
-                    } else if (SPILL) {
-                        tsb[i] = kNoSpill;
                     }
                     tcnt[i] = 0;
-                } else if (SPILL) {
-                    tss[i] = tsb[i] = kNoSpill;
-                }
-            }
-            if (a.bin_fill) {                      // only when the host sizes the bins of a new shape
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    fs = max(fs, __shfl_xor(fs, off));
-                    fb = max(fb, __shfl_xor(fb, off));
-                }
-                if ((threadIdx.x & 63) == 0 && (fs | fb)) {
-                    atomicMax(a.bin_fill, fs);
-                    atomicMax(a.bin_fill + 1, fb);
                 }
             }
             __syncthreads();
@@ -782,9 +765,10 @@ __global__ void __launch_bounds__(kWG, 6) k_bin(BatchDesc bd, RasterArgs a, int3
                 }
                 __syncthreads();
                 if (band_spill == 2u)
-                    for (int i = threadIdx.x; i < nb; i += kWG)
-                        if (tss[i] != kNoSpill || tsb[i] != kNoSpill)
-                            a.spill_lost[rec0 + (by0 + i / rw) * sd.tiles_x + rx0 + i % rw] = 1;
+                    for (uint32_t m = spilled; m; m &= m - 1) {
+                        const int i = threadIdx.x + (__ffs(m) - 1) * kWG;
+                        a.spill_lost[rec0 + (by0 + i / rw) * sd.tiles_x + rx0 + i % rw] = 1;
+                    }
             }
             const bool band_ok = !SPILL || band_spill == 1u;
             const uint32_t sbase = SPILL ? (uint32_t)band_base : 0u;
@@ -828,6 +812,18 @@ __global__ void __launch_bounds__(kWG, 6) k_bin(BatchDesc bd, RasterArgs a, int3
             if (by0 > ry1) break;
             __syncthreads();                   // the put cursors of this band are no longer read
             for (int i = threadIdx.x; i < brows * rw; i += kWG) tcnt[i] = 0;
+        }
+    }
+    if (a.bin_fill) {                          // only when the host sizes the bins of a new shape
+        // (once per wave at the end: per band, these few addresses were contended)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            fs = max(fs, __shfl_xor(fs, off));
+            fb = max(fb, __shfl_xor(fb, off));
+        }
+        if ((threadIdx.x & 63) == 0 && (fs | fb)) {
+            atomicMax(a.bin_fill, fs);
+            atomicMax(a.bin_fill + 1, fb);
         }
     }
 }
