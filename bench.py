@@ -33,17 +33,17 @@ HBM_PEAK_GBS = 8000.0
 # DRAM bytes of one rasterizer launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # scaled by a plain-copy calibration (profiles/k_raster_differentiation.md);
 # valid only for the rasterizer source and tile they were taken with.
-PROFILED_TRAFFIC = {"rm_raster_sha256_16": "971c273d06cd6d00", "tile": [64, 32],
+PROFILED_TRAFFIC = {"rm_raster_sha256_16": "dbc145b4dde8bc66", "tile": [64, 32],
                     # calibrated FETCH_SIZE + WRITE_SIZE of one rasterizer and one
                     # binning launch, and the rasterizer's VALU issue fraction
                     # (profiles/k_raster_differentiation.md)
-                    "bytes_per_launch": 1274.0e6, "bin_bytes_per_launch": 1217.3e6, "valu_issue_frac": 0.784,
+                    "bytes_per_launch": 1327.2e6, "bin_bytes_per_launch": 1218.2e6, "valu_issue_frac": 0.817,
                     # SQ_INSTS_LDS_ATOMIC_BANDWIDTH x 8: 64-bit LDS atomic lanes of one
                     # rasterizer launch (an upper bound: the few 32-bit queue counters
                     # count as well), and TCC_ATOMIC_sum of one binning launch and its
                     # profiled duration (profiles/atomics_differentiation.md)
-                    "lds_atomic_lanes_per_launch": 1.914e8, "bin_global_atomics_per_launch": 7.428e5,
-                    "bin_launch_ms": 0.937}
+                    "lds_atomic_lanes_per_launch": 1.924e8, "bin_global_atomics_per_launch": 7.428e5,
+                    "bin_launch_ms": 0.931}
 
 
 def profiled_traffic(tile, field="bytes_per_launch"):

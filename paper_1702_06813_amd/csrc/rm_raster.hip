@@ -300,14 +300,14 @@ struct Queues {
     float rowmin[2][kSnapTile + 1];
 };
 
-__device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, const float* rmin, const Tile& tl,
+__device__ __forceinline__ bool emit_tri(uint64_t* keys, int tile_w, Queues& Q, const float* rmin, const Tile& tl,
                                          const CamF& cam, float3 A, float3 B, float3 C, const WPlane& pl,
                                          uint32_t id) {
     int X[3], Y[3];
-    if (!snap(cam, A, X[0], Y[0]) || !snap(cam, B, X[1], Y[1]) || !snap(cam, C, X[2], Y[2])) return;
+    if (!snap(cam, A, X[0], Y[0]) || !snap(cam, B, X[1], Y[1]) || !snap(cam, C, X[2], Y[2])) return true;
     const int64_t area = (int64_t)(X[1] - X[0]) * (int64_t)(Y[2] - Y[0]) -
                          (int64_t)(Y[1] - Y[0]) * (int64_t)(X[2] - X[0]);
-    if (area == 0) return;
+    if (area == 0) return true;
     if (area < 0) {
         int t = X[1]; X[1] = X[2]; X[2] = t;
         t = Y[1]; Y[1] = Y[2]; Y[2] = t;
@@ -316,14 +316,16 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     const int mny = min(Y[0], min(Y[1], Y[2])), mxy = max(Y[0], max(Y[1], Y[2]));
     const int px0 = max((mnx + 255) >> 8, tl.x0), px1 = min(mxx >> 8, tl.x1);
     const int py0 = max((mny + 255) >> 8, tl.y0), py1 = min(mxy >> 8, tl.y1);
-    if (px0 > px1 || py0 > py1) return;
+    if (px0 > px1 || py0 > py1) return true;
     const int boxpx = (px1 - px0 + 1) * (py1 - py0 + 1);
     const uint32_t box = (uint32_t)(px0 - tl.x0) | ((uint32_t)(px1 - tl.x0) << 8) | ((uint32_t)(py0 - tl.y0) << 16) |
                          ((uint32_t)(py1 - tl.y0) << 24);
     if (boxpx <= kSmallArea && mxx - mnx < (1 << 14) && mxy - mny < (1 << 14)) {
         raster_small(keys, tile_w, tl, rmin, X, Y, px0, px1, py0, py1, pl, (double)cam.cx, (double)cam.cy, id);
-        return;
+        return true;
     }
+    const int k = atomicAdd(&Q.big.n, 1);
+    if (k >= kQCap) return false;              // queue full: queued again in another pass of the round
     int Xr[3], Yr[3];
     double m[3];
 #pragma unroll
@@ -334,12 +336,6 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
         Yr[i] = Y[i] - 256 * tl.y0;
         m[i] = dy != 0 ? (double)dx / (double)dy : 0.0;
     }
-    const int k = atomicAdd(&Q.big.n, 1);
-    if (k >= kQCap) {                          // queue full: this thread walks the rows itself
-        raster_rows(keys, tile_w, tl, rmin, Xr, Yr, m, pl.a, pl.b, pl.e, id, px0 - tl.x0, px1 - tl.x0, py0 - tl.y0,
-                    py1 - tl.y0, (double)cam.cx, (double)cam.cy);
-        return;
-    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) { Q.big.X[i][k] = Xr[i]; Q.big.Y[i][k] = Yr[i]; Q.big.m[i][k] = m[i]; }
     Q.big.pa[k] = pl.a; Q.big.pb[k] = pl.b; Q.big.pe[k] = pl.e;
@@ -348,6 +344,7 @@ __device__ __forceinline__ void emit_tri(uint64_t* keys, int tile_w, Queues& Q, 
     const int b0 = (py0 - tl.y0) / kBand, b1 = (py1 - tl.y0) / kBand;
     const int j0 = atomicAdd(&Q.big.njobs, b1 - b0 + 1);
     for (int b = b0; b <= b1; ++b) Q.big.job[j0 + b - b0] = (uint16_t)((k << 4) | b);
+    return true;
 }
 
 __device__ __forceinline__ float3 sel3(int k, float3 a, float3 b, float3 c) {
@@ -382,19 +379,21 @@ __device__ __forceinline__ void load_vertices(const float* __restrict__ xyz, int
 }
 
 // Whole contract for one mesh triangle: transform, far cull, near clip into
-// at most two sub-triangles (same id), setup and rasterization.
+// at most two sub-triangles (same id), setup and rasterization.  Sub-triangle
+// k is left out where bit k of skip is set; returns the mask of the
+// sub-triangles that found the band queue full (0: the triangle is done).
 template <int MODE>
-__device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queues& q, const float* rmin,
-                                                const Tile& tl, const CamF& cam, double ifx, double ify,
-                                                const PoseF& P, const TriIn& in) {
+__device__ __forceinline__ int raster_triangle(uint64_t* keys, int tile_w, Queues& q, const float* rmin,
+                                               const Tile& tl, const CamF& cam, double ifx, double ify,
+                                               const PoseF& P, const TriIn& in, int skip) {
     const float x0 = in.v[0], y0 = in.v[1], z0 = in.v[2];
     const float3 V0 = cam_contract(P, x0, y0, z0);
     const float3 V1 = cam_contract(P, in.v[3], in.v[4], in.v[5]);
     const float3 V2 = cam_contract(P, in.v[6], in.v[7], in.v[8]);
-    if (V0.z > cam.zf && V1.z > cam.zf && V2.z > cam.zf) return;
+    if (V0.z > cam.zf && V1.z > cam.zf && V2.z > cam.zf) return 0;
     const bool in0 = V0.z >= cam.zn, in1 = V1.z >= cam.zn, in2 = V2.z >= cam.zn;
     const int nin = (int)in0 + (int)in1 + (int)in2;
-    if (nin == 0) return;
+    if (nin == 0) return 0;
     const PlaneN pn = plane_normal(P, in.v);
     // 1/z over the triangle peaks at its nearest vertex; one pixel of plane
     // extrapolation covers the snapping.  Behind the tile's farthest key at
@@ -408,14 +407,14 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
         pl = depth_plane(pn, ifx, ify);
         if (nin == 3) {
             const double wv = 1.0 / (double)fminf(V0.z, fminf(V1.z, V2.z)) + fabs(pl.a) + fabs(pl.b);
-            if (wv * 1.00001 < (double)rmin[kSnapTile]) return;
+            if (wv * 1.00001 < (double)rmin[kSnapTile]) return 0;
         }
     } else {
         if (nin == 3) {
             const double zmin = (double)fminf(V0.z, fminf(V1.z, V2.z));
             const double ac = fabs(pn.c);
             const double lhs = (ac + zmin * (fabs(pn.nx) * ifx + fabs(pn.ny) * ify)) * 1.00001;
-            if (lhs < (double)rmin[kSnapTile] * zmin * ac) return;
+            if (lhs < (double)rmin[kSnapTile] * zmin * ac) return 0;
         }
         pl = depth_plane(pn, ifx, ify);
     }
@@ -441,11 +440,14 @@ __device__ __forceinline__ void raster_triangle(uint64_t* keys, int tile_w, Queu
         const float3 b = sel3(k == 0 ? 2 : k - 1, V0, V1, V2);
         A0 = I; B0 = clip_point(I, a, cam.zn); C0 = clip_point(I, b, cam.zn);
     }
+    int left = 0;
 #pragma unroll 1
     for (int sub = 0; sub < nsub; ++sub) {
+        if ((skip >> sub) & 1) continue;
         const float3 A = sub ? A1 : A0, B = sub ? B1 : B0, C = sub ? C1 : C0;
-        emit_tri(keys, tile_w, q, rmin, tl, cam, A, B, C, pl, id);
+        if (!emit_tri(keys, tile_w, q, rmin, tl, cam, A, B, C, pl, id)) left |= 1 << sub;
     }
+    return left;
 }
 
 // ------------------------------------------------------------------ binning
@@ -1062,10 +1064,29 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         load_indices(a.tri, a.vmax, t2, I2);
         t3 = entry(r + 3);
         __syncthreads();
-        if (cur.t >= 0) raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, P, cur);
-        __syncthreads();
-        if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy);
-        __syncthreads();
+        // A sub-triangle that finds the band queue full is queued in another
+        // pass once the queue has been drained; only its triangle id and the
+        // mask of pending sub-triangles stay live, its inputs are gathered
+        // again (queue passes beyond the first are rare).
+        int left = cur.t >= 0 ? raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, P, cur, 0) : 0;
+        int32_t t_left = left ? cur.t : -1;
+        for (;;) {
+            __syncthreads();
+            const bool more = q.big.n > kQCap;   // some sub-triangle found the queue full
+            if (q.big.njobs) raster_queue<TW, TH>(keys, q.big, tl, rmin, dcx, dcy);
+            __syncthreads();
+            if (!more) break;
+            if (tid == 0) { q.big.n = 0; q.big.njobs = 0; }
+            __syncthreads();
+            if (t_left >= 0) {
+                TriIn tri;
+                uint32_t I[3];
+                load_indices(a.tri, a.vmax, t_left, I);
+                load_vertices(a.xyz, t_left, I, tri);
+                left = raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, P, tri, ~left & 3);
+                if (!left) t_left = -1;
+            }
+        }
         // row and tile snapshot for the next round (w >= 0, so its bits order
         // like its value).  Pixel p = tid + k kWG lies in row p / TW, so the
         // kG lanes of a group cover one kSeg-pixel segment (or, for 8-pixel
