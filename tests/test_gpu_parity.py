@@ -231,6 +231,52 @@ def test_render_deep_stack_many_rounds(rm):
             rm.context().set_tile(0, 0)
 
 
+def _big_overlap(seed, n=900):
+    """n large triangles over the 64x48 view of the identity camera, at
+    random depths 0.6 .. 3.0 m, each spanning most of the view; every third
+    has one vertex, every ninth two, in front of the near plane (down to
+    behind the camera, off to a side), so that it is clipped into two
+    sub-triangles or one.
+    Triangle ids shuffled."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for k in range(n):
+        z = rng.uniform(0.6, 3.0, size=3)
+        ang = rng.uniform(0, 2 * np.pi) + np.array([0.0, 2.1, 4.2]) + rng.uniform(-0.3, 0.3, 3)
+        r = rng.uniform(0.6, 1.1, 3)
+        x, y = 0.6 * r * np.cos(ang) * z, 0.45 * r * np.sin(ang) * z
+        side = rng.choice([-1.0, 1.0])
+        for j in range(1 + (k % 9 == 0) if k % 3 == 0 else 0):
+            # off to one side, so that the part near the camera leaves the view
+            z[j] = rng.uniform(-0.3, 0.08)
+            x[j], y[j] = side * rng.uniform(0.6, 1.0), rng.uniform(-0.3, 0.3)
+        pts.append(np.stack([x, y, z], 1))
+    xyz = np.concatenate(pts).astype(np.float32)
+    tri = np.arange(3 * n, dtype=np.int32).reshape(n, 3)[rng.permutation(n)]
+    return xyz, tri, np.zeros(n, np.uint8)
+
+
+def test_render_band_queue_overflow(rm):
+    """900 large, overlapping triangles over one 64x48 view: the first round
+    of a tile offers 256 of them, every one above the in-thread size and none
+    culled yet, so more sub-triangles ask for the band queue than it holds
+    and the round takes further queue passes; near-plane crossings split
+    triangles in two, so some threads come back with only their second
+    sub-triangle.  Full-frame parity with the oracle at three tile shapes."""
+    _say("render band queue overflow")
+    mesh = _big_overlap(31)
+    cam = S.Camera(52.5, 52.5, 31.5, 23.5, 64, 48, z_near=0.1, z_far=16.0)
+    T = np.zeros((3, 4)); T[:, :3] = np.eye(3)
+    rng = np.random.default_rng(37)
+    poses = [T] + [S.perturb(T, rng, 0.05, np.deg2rad(3)) for _ in range(3)]
+    for tile in ((64, 32), (32, 32), (16, 16)):
+        rm.context().set_tile(*tile)
+        try:
+            _render_cmp(rm, mesh, cam, poses)
+        finally:
+            rm.context().set_tile(0, 0)
+
+
 def test_duplicate_triangles_lowest_id_wins(rm):
     """Every triangle of the tiny room twice, the two copies at shuffled
     positions (ids): at every pixel the GPU's triangle id is the lower id of
