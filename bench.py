@@ -32,8 +32,9 @@ METRIC = "pose cost+grad evals/s @640x480, 1M-tri mesh; scans aligned/s vs plain
 HBM_PEAK_GBS = 8000.0
 # DRAM bytes of one rasterizer launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
 # scaled by a plain-copy calibration (profiles/k_raster_differentiation.md);
-# valid only for the rasterizer source and tile they were taken with.
-PROFILED_TRAFFIC = {"rm_raster_sha256_16": "dbc145b4dde8bc66", "tile": [64, 32],
+# valid only for the rasterizer source and tile they were taken with (the
+# prefix moves with a comment-only edit whose device assembly is unchanged).
+PROFILED_TRAFFIC = {"rm_raster_sha256_16": "cf7798a3c4dbfc6a", "tile": [64, 32],
                     # calibrated FETCH_SIZE + WRITE_SIZE of one rasterizer and one
                     # binning launch, and the rasterizer's VALU issue fraction
                     # (profiles/k_raster_differentiation.md)

@@ -195,7 +195,7 @@ __device__ __forceinline__ void raster_small(uint64_t* keys, int tile_w, const T
 // workgroup in jobs of kBand rows: a job brackets the covered span of each of
 // its rows between the three edge crossings (FP64, exact to far below a
 // pixel) and gives only pixel centres inside it the exact int64 edge test.
-constexpr int kQCap = 192;                 // queued sub-triangles per round (more go in-thread); with the
+constexpr int kQCap = 192;                 // queued sub-triangles per pass (more wait for the next); with the
                                            // 16 KB z-buffer, 40 KB of LDS: four workgroups per CU
 constexpr int kBand = 2;                   // rows per job
 constexpr int kSmallArea = 64;             // bounding-box pixels rasterized by the owning thread
@@ -1067,7 +1067,8 @@ __device__ __forceinline__ void tile_pass(const BatchDesc& bd, const RasterArgs&
         // A sub-triangle that finds the band queue full is queued in another
         // pass once the queue has been drained; only its triangle id and the
         // mask of pending sub-triangles stay live, its inputs are gathered
-        // again (queue passes beyond the first are rare).
+        // again (only rounds with more large sub-triangles than the queue
+        // holds, mostly a bin's first rounds, take further passes).
         int left = cur.t >= 0 ? raster_triangle<MODE>(keys, TW, q, rmin, tl, cam, difx, dify, P, cur, 0) : 0;
         int32_t t_left = left ? cur.t : -1;
         for (;;) {
