@@ -541,6 +541,8 @@ def main():
     ap.add_argument("--no-alignment", action="store_true", help="skip the batched-vs-plain alignment comparison")
     ap.add_argument("--no-icp", action="store_true", help="skip the render-accelerated ICP odometry (Sec. V)")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
+    ap.add_argument("--configs", default="tiny,kinect,wide,uneven",
+                    help="comma-separated workloads for the throughput lines (tiny, kinect, wide, uneven)")
     ap.add_argument("--no-trajectory", action="store_true", help="skip the 500-scan trajectory alignment")
     ap.add_argument("--no-color", action="store_true", help="skip the color term's throughput and wall alignment")
     ap.add_argument("--atomic-peaks", action="store_true",
@@ -678,8 +680,13 @@ def main():
     if not args.no_icp:
         res["icp_odometry"] = icp_odometry(rm, torch, dev)
     if not args.no_configs:
-        res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in ("tiny", "kinect", "wide")}
-        res["configs"]["uneven"] = uneven_stream(rm, torch, dev)
+        names = [n for n in args.configs.split(",") if n]
+        unknown = sorted(set(names) - {"tiny", "kinect", "wide", "uneven"})
+        if unknown:
+            raise SystemExit(f"bench.py: unknown workload(s) in --configs: {', '.join(unknown)}")
+        res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in names if name != "uneven"}
+        if "uneven" in names:
+            res["configs"]["uneven"] = uneven_stream(rm, torch, dev)
     if not args.no_trajectory:
         res["trajectory"] = trajectory_c5(rm, torch, dev)
     if not args.no_color:
