@@ -554,6 +554,12 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the pose-scoring path is built and "
               f"measured on a single MI355X", file=sys.stderr)
         sys.exit(2)
+    config_names = [n for n in args.configs.split(",") if n]
+    unknown = sorted(set(config_names) - {"tiny", "kinect", "wide", "uneven"})
+    if unknown:
+        print(f"bench.py: unknown workload(s) in --configs: {', '.join(unknown)} "
+              f"(known: tiny, kinect, wide, uneven)", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     import paper_1702_06813_amd as rm
@@ -680,12 +686,8 @@ def main():
     if not args.no_icp:
         res["icp_odometry"] = icp_odometry(rm, torch, dev)
     if not args.no_configs:
-        names = [n for n in args.configs.split(",") if n]
-        unknown = sorted(set(names) - {"tiny", "kinect", "wide", "uneven"})
-        if unknown:
-            raise SystemExit(f"bench.py: unknown workload(s) in --configs: {', '.join(unknown)}")
-        res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in names if name != "uneven"}
-        if "uneven" in names:
+        res["configs"] = {name: config_throughput(rm, torch, dev, name) for name in config_names if name != "uneven"}
+        if "uneven" in config_names:
             res["configs"]["uneven"] = uneven_stream(rm, torch, dev)
     if not args.no_trajectory:
         res["trajectory"] = trajectory_c5(rm, torch, dev)
