@@ -277,6 +277,30 @@ def test_render_band_queue_overflow(rm):
             rm.context().set_tile(0, 0)
 
 
+def test_cost_grad_band_queue_overflow(rm):
+    """Cost, gradient and Gauss-Newton blocks through the rounds that take
+    further band-queue passes: the 900 overlapping triangles against a scan
+    the oracle renders from a nearby pose, four poses, at two tile shapes,
+    against the oracle's reduction over its unflagged pixels."""
+    _say("cost+grad band queue overflow")
+    mesh = _big_overlap(31)
+    cam = S.Camera(52.5, 52.5, 31.5, 23.5, 64, 48, z_near=0.1, z_far=16.0)
+    T = np.zeros((3, 4)); T[:, :3] = np.eye(3)
+    rng = np.random.default_rng(41)
+    rend = O.render(mesh, cam, S.perturb(T, rng, 0.02, np.deg2rad(1)), None)
+    depth = np.zeros(cam.width * cam.height, np.float32)
+    hit = rend["id"] >= 0
+    depth[rend["pixels"][hit]] = rend["z"][hit]
+    depth = depth.reshape(cam.height, cam.width)
+    poses = [T] + [S.perturb(T, rng, 0.03, np.deg2rad(2)) for _ in range(3)]
+    for tile in ((64, 32), (16, 16)):
+        rm.context().set_tile(*tile)
+        try:
+            _cost_case_scan(rm, mesh, cam, depth, 0.05, 8.0, poses, None)
+        finally:
+            rm.context().set_tile(0, 0)
+
+
 def test_duplicate_triangles_lowest_id_wins(rm):
     """Every triangle of the tiny room twice, the two copies at shuffled
     positions (ids): at every pixel the GPU's triangle id is the lower id of
